@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Forward + inverse shearlet filter-bank throughput on one MI355X.
+
+Workload: batch 16 of 512x512 synthetic cartoon images plus N(0, 30^2)
+noise, 4-scale system with shear levels (1, 1, 2, 2) -> 49 filters, FP32.
+One step = shear_forward then shear_inverse of the whole batch (every step
+of the hot path), inputs resident in HBM before the timed region.
+
+Prints ONE JSON line: the throughput in Mpix*filters/s (B*N*M*K per step),
+the roofline of the dominant kernel (per-launch hipEvents over the timed
+region, on the stream the kernels run on), the whole-path roofline, and the
+FP64 oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+inv shearlet Mpix·filters/s @512²×49 FP32; % of HBM roofline"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+B, N, M, J = 16, 512, 512, 4
+SIGMA = 30.0
+WORKLOAD = "fwd+inv, 16 x 512x512 cartoon+N(0,30^2) images, 4 scales (shear levels 1,1,2,2) = 49 filters, FP32"
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
+    """Algorithmic bytes of one launch of each kernel kind at this workload (one launch per call, no chunking).
+
+    The method must read x and the filter bank and write the coefficients in the
+    forward transform, and read the coefficients and the filter bank and write
+    the images in the inverse. Each of these compulsory transfers is attributed
+    to the kernel that performs it; exchange intermediates count as overhead.
+    """
+    img = B * N * M * 4
+    coef = B * K * N * M * 4
+    filt = K * N * (M // 2 + 1) * (4 if real_filters else 8)
+    return {
+        "rows_r2c_images": img,
+        "cols_fwd": filt,
+        "rows_c2r_coeffs": coef,
+        "rows_r2c_coeffs": coef,
+        "cols_inv": filt,
+        "rows_c2r_images": img,
+    }[kind]
+
+
+def path_algorithmic_bytes(K: int, real_filters: bool) -> float:
+    """Whole fwd+inv step: x in, c out, c in, y out, filter bank read once per direction."""
+    filt = K * N * (M // 2 + 1) * (4 if real_filters else 8)
+    return B * (8 * N * M + 8 * K * N * M) + 2 * filt
+
+
+def traffic_from_profiles(kind: str, per_launch_units: float):
+    """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json), if the
+    kernel source has not changed since; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2006_04591_amd", "csrc", "kernels.hip")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+        with open(src, "rb") as fh:
+            digest = hashlib.sha256(fh.read()).hexdigest()
+        if rec.get("kernels_hip_sha256") != digest:
+            return None
+        ent = rec["kernels"].get(kind)
+        return None if ent is None else float(ent["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(x_host, n_images: int) -> dict:
+    """The FP64 oracle (numpy, as it stands) on a bounded sample: fwd+inv of n_images images."""
+    import numpy as np
+
+    from oracle import filters as OF
+    from oracle import transform as OT
+
+    log(f"cpu baseline: oracle system build 512x512 J={J}")
+    ref = OF.build_system(N, M, J)
+    t0 = time.perf_counter()
+    for b in range(n_images):
+        c = OT.forward_plain(x_host[b].astype(np.float64), ref.spectra)
+        OT.inverse_plain(c, ref.spectra, ref.W)
+        log(f"cpu baseline: image {b + 1}/{n_images} done")
+    dt = time.perf_counter() - t0
+    units = n_images * N * M * ref.K / 1e6
+    return {
+        "value": units / dt,
+        "unit": "Mpix·filters/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"numpy FP64 oracle, fwd+inv of {n_images} of the 16 images (512x512, 49 filters), "
+                  f"{dt:.1f} s; numpy.fft runs single-threaded",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--cpu-images", type=int, default=2, help="images in the oracle baseline sample (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); run with --gpus 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2006_04591_amd import ShearletSystem
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    log("bench: building system 512x512 J=4")
+    t0 = time.perf_counter()
+    shs = ShearletSystem.build(N, M, J)
+    build_s = time.perf_counter() - t0
+    K = shs.K
+    S, _ = shs.export_spectra()
+    real_filters = bool(np.all(S.imag == 0))
+    log(f"bench: K={K}, build {build_s:.2f} s, real filters={real_filters}")
+    x_host = synth.cartoon_batch(B, N, M, config=2, sigma=SIGMA)
+    x = torch.from_numpy(x_host).to(dev)
+    c = torch.empty((B, K, N, M), dtype=torch.float32, device=dev)
+    y = torch.empty((B, N, M), dtype=torch.float32, device=dev)
+    shs.reserve(B)
+
+    def step():
+        shs.forward(x, out=c)
+        shs.inverse(c, out=y)
+
+    for i in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"bench: {args.warmup} warmup steps done")
+
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    shs.profile(True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for i in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    rec = shs.profile_read()
+    shs.profile(False)
+    ms_step = ms_total / args.steps
+    log(f"bench: {args.steps} timed steps, {ms_step:.3f} ms/step")
+
+    # correctness guard on the timed output: reconstruction of the inputs
+    err = float(torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x))
+    if not err <= 1e-5:
+        print(f"bench.py: reconstruction error {err:.3e} exceeds 1e-5", file=sys.stderr)
+        return 1
+
+    units = B * N * M * K / 1e6
+    value = units / (ms_step / 1e3)
+    kernels = {}
+    for kind, (n, tot) in rec.items():
+        if n == 0:
+            continue
+        avg = tot / n
+        ab = kernel_algorithmic_bytes(kind, K, real_filters)
+        kernels[kind] = {"launches": n, "avg_ms": avg, "share": tot / ms_total,
+                         "algorithmic_GBs": ab / (avg / 1e3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    dk = kernels[dom]
+    ab = kernel_algorithmic_bytes(dom, K, real_filters)
+    achieved = ab / (dk["avg_ms"] / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(dom, 1.0),
+                "kernel": dom, "avg_launch_ms": dk["avg_ms"], "algorithmic_bytes_per_launch": ab}
+    pb = path_algorithmic_bytes(K, real_filters)
+    path = {"bound": "hbm", "achieved": pb / (ms_step / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": pb / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_step": pb}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mpix·filters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "batch": B, "rows": N, "cols": M, "filters": K, "shear_levels": [1, 1, 2, 2]},
+        "roofline": roofline,
+        "path_roofline": path,
+        "kernels": kernels,
+        "reconstruction_rel_err": err,
+        "system_build_s": build_s,
+    }
+    if args.cpu_images > 0:
+        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_images)
+    shs.close()
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

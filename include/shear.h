@@ -1,0 +1,157 @@
+/*
+ * shear.h -- C ABI of the MI355X (gfx950) digital shearlet filter-bank library.
+ *
+ * The transform follows "tfShearlab: The TensorFlow Digital Shearlet Transform
+ * for Deep Learning" (Andrade-Loarca, Kutyniok):
+ *   - system construction: Section 3.4.1 (getshearletsystem2D), built from the
+ *     digital construction of Section 2.1 (eqs. (2.1)-(2.6));
+ *   - forward transform (decomposition): Algorithm 1 and its listing
+ *     (tfsheardec2D), Section 3.4.2;
+ *   - inverse transform (reconstruction): Algorithm 2 and its listing
+ *     (tfshearrec2D), Section 3.4.2, with the dual-frame weight
+ *     W = sum_k |Psi_k|^2;
+ *   - adjoint: Algorithm 2 without the division by W.
+ *
+ * Conventions shared by every entry point
+ *   Images are float32, row-major (C order): x[b][r][c], r < rows, c < cols.
+ *   Coefficients are float32, planar, row-major: coeffs[b][k][r][c], k < K.
+ *   The 2-D DFT is unnormalised and its inverse carries 1/(rows*cols), so
+ *     coeffs[b][k] = Re ifft2( fft2(x[b]) * conj(Psi_k) ),
+ *     x_rec[b]     = Re ifft2( sum_k fft2(coeffs[b][k]) * Psi_k / W ),
+ *     adjoint[b]   = Re ifft2( sum_k fft2(coeffs[b][k]) * Psi_k ).
+ *   Spectra at this interface use the paper's centred layout (index
+ *   (rows/2, cols/2) is zero frequency, i.e. fftshift of the DFT order) and
+ *   are FP64 (re, im) pairs: spectra[k][r][c][2].
+ *   Filter order: for scale j = 1..J: cone 1 shears -2^s..2^s, then cone 2
+ *   shears -(2^s-1)..(2^s-1), s = shear level of scale j; low-pass last.
+ *   Index triples are (cone, scale, shear); the low-pass is (0, 0, 0).
+ *
+ * Sizes: the GPU path takes rows, cols powers of two in [16, 1024].
+ *
+ * Ownership and ordering
+ *   The caller owns x / coeffs (device memory, e.g. torch tensors) and keeps
+ *   them alive until work queued on the stream has finished. A system owns its
+ *   device filter sets, twiddle tables and workspace. Transform calls are
+ *   asynchronous on the given HIP stream (NULL = default stream) and never
+ *   synchronise the host, except when the workspace must grow (first call with
+ *   a larger batch; see shear_reserve). Only one call per system may be in
+ *   flight at a time: calls on different streams sharing a system race on its
+ *   workspace.
+ *
+ * Errors: every int-returning call returns SHEAR_OK or a negative code; no
+ * C++ exception crosses this boundary. shear_last_error() gives a message for
+ * the most recent failure on the calling thread. Asynchronous kernel faults
+ * surface at the caller's next synchronisation. NaN/Inf inputs propagate.
+ */
+#ifndef SHEAR_H
+#define SHEAR_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SHEAR_OK 0
+#define SHEAR_E_INVALID (-1) /* null pointer, non-positive batch or count, bad parameter */
+#define SHEAR_E_SIZE (-2)    /* size not supported, or a constructed kernel does not fit */
+#define SHEAR_E_FRAME (-3)   /* min W <= 1e-10 max W, or non-Hermitian spectra */
+#define SHEAR_E_NOMEM (-4)   /* device or host allocation failed / workspace cap too small */
+#define SHEAR_E_HIP (-5)     /* a HIP API call or kernel launch failed */
+#define SHEAR_E_DEVICE (-6)  /* current device is not the device the system was built on */
+
+typedef struct shear_system shear_system; /* opaque */
+
+typedef struct {
+    int rows;                   /* image rows N */
+    int cols;                   /* image columns M */
+    int n_scales;               /* J >= 1 */
+    const int* shear_levels;    /* J entries (each 0..4), or NULL for ceil(j/2), j = 1..J */
+    const double* scaling_taps; /* odd-length real 1-D low-pass h, centred; NULL = default
+                                   9-tap maxflat design of Section 3.4.1 */
+    int n_scaling;              /* length of scaling_taps */
+    const double* fan_taps;     /* real 2-D fan filter P, row-major fan_rows x fan_cols, odd
+                                   sizes, centred; NULL = default maxflat fan of Section 3.4.1 */
+    int fan_rows, fan_cols;
+    size_t max_workspace_bytes; /* cap on the device workspace; 0 = 4 GiB */
+} shear_build_params;
+
+/* Host only, no device needed (Section 3.4.1 construction, FP64).
+ * Computes the filter bank described by p. *K receives the number of filters.
+ * spectra_centred (K*rows*cols*2 doubles) and idx (K*3 ints) may be NULL to
+ * query K only. Returns SHEAR_E_SIZE when a kernel does not fit in rows x cols
+ * or the sizes are outside [4, 4096]. */
+int shear_design_spectra(const shear_build_params* p, int* K, double* spectra_centred, int* idx);
+
+/* getshearletsystem2D (Section 3.4.1): builds the system on the current device.
+ * Synchronous. *out receives a new system; free it with shear_destroy_system. */
+int shear_build_system(const shear_build_params* p, shear_system** out);
+
+/* A system from caller-supplied spectra (centred layout, K*rows*cols*2 doubles,
+ * host memory, copied). The spectra must be Hermitian (DFTs of real kernels):
+ * |Psi(-xi) - conj Psi(xi)| <= 1e-9 max|Psi|, else SHEAR_E_FRAME; the frame
+ * must satisfy min W > 1e-10 max W, else SHEAR_E_FRAME. idx may be NULL
+ * (triples then read (0, 0, k)). Synchronous. */
+int shear_system_from_spectra(int rows, int cols, int K, const double* spectra_centred, const int* idx,
+                              size_t max_workspace_bytes, shear_system** out);
+
+/* Sizes, RMS_k = ||Psi_k||_F / sqrt(rows*cols) (K doubles) and index triples
+ * (K*3 ints) of a system. Any output pointer may be NULL. Host only. */
+int shear_system_info(const shear_system* s, int* K, int* rows, int* cols, double* rms, int* idx);
+
+/* Copies the FP64 spectra (centred, K*rows*cols*2 doubles) and the dual-frame
+ * weight W (centred, rows*cols doubles) to host memory; either may be NULL. */
+int shear_export_spectra(const shear_system* s, double* spectra_centred, double* W_centred);
+
+/* Allocates the device workspace for batches up to `batch`, so that later
+ * transform calls with batch <= `batch` never allocate. Synchronous. */
+int shear_reserve(shear_system* s, int batch);
+
+/* Device bytes the workspace needs for one call with `batch` images. */
+int shear_workspace_bytes(const shear_system* s, int batch, size_t* bytes);
+
+/* tfsheardec2D / Algorithm 1 (Section 3.4.2): x (batch*rows*cols float32,
+ * device) -> coeffs (batch*K*rows*cols float32, device). Asynchronous on
+ * hip_stream (a hipStream_t, NULL = default). x and coeffs must not overlap. */
+int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, void* hip_stream);
+
+/* tfshearrec2D / Algorithm 2 (Section 3.4.2): coeffs -> x, dividing the
+ * filtered sum by the dual-frame weight W. Asynchronous. */
+int shear_inverse(shear_system* s, const float* coeffs, float* x, int batch, void* hip_stream);
+
+/* Adjoint SH* of shear_forward (Algorithm 2 without the division by W):
+ * <shear_forward(x), c> = <x, shear_adjoint(c)>. Asynchronous. */
+int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, void* hip_stream);
+
+/* Launch kinds reported by shear_profile_read (one kernel symbol each). */
+#define SHEAR_KERNEL_ROWS_R2C_IMAGES 0 /* forward: row FFT of the images              */
+#define SHEAR_KERNEL_COLS_FWD 1        /* forward: column FFT, x conj filter, IFFT (K-expanding) */
+#define SHEAR_KERNEL_ROWS_C2R_COEFFS 2 /* forward: row inverse FFT -> coefficient planes */
+#define SHEAR_KERNEL_ROWS_R2C_COEFFS 3 /* inverse/adjoint: row FFT of the coefficient planes */
+#define SHEAR_KERNEL_COLS_INV 4        /* inverse/adjoint: column FFT, x filter, sum over k, IFFT */
+#define SHEAR_KERNEL_ROWS_C2R_IMAGES 5 /* inverse/adjoint: row inverse FFT -> images   */
+#define SHEAR_KERNEL_KINDS 6
+
+/* Per-launch timing (tracing). While enabled, every kernel launch of the
+ * system is bracketed by two hipEvents recorded on the caller's stream. */
+int shear_profile_enable(shear_system* s, int on);
+
+/* Waits for the recorded events, then writes per kind the number of launches
+ * and their summed duration in ms (arrays of SHEAR_KERNEL_KINDS) since the
+ * previous read, and clears the record. */
+int shear_profile_read(shear_system* s, int* launches, double* total_ms);
+
+/* Frees a system. The caller must have synchronised every stream that used it. */
+void shear_destroy_system(shear_system* s);
+
+/* Static description of an error code. */
+const char* shear_strerror(int code);
+
+/* Detail message of the most recent failure on the calling thread ("" if none). */
+const char* shear_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHEAR_H */

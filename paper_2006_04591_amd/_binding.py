@@ -1,0 +1,298 @@
+"""ctypes binding of libshear.so (include/shear.h). Argument marshalling only.
+
+Every transform step runs in the HIP library; PyTorch supplies device memory
+(tensor data pointers) and the current HIP stream. There is no fallback: if
+the library is missing or fails to load, using the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libshear.so")
+
+SHEAR_OK = 0
+ERRORS = {
+    -1: "SHEAR_E_INVALID",
+    -2: "SHEAR_E_SIZE",
+    -3: "SHEAR_E_FRAME",
+    -4: "SHEAR_E_NOMEM",
+    -5: "SHEAR_E_HIP",
+    -6: "SHEAR_E_DEVICE",
+}
+
+EXPORTED = (
+    "shear_design_spectra",
+    "shear_build_system",
+    "shear_system_from_spectra",
+    "shear_system_info",
+    "shear_export_spectra",
+    "shear_reserve",
+    "shear_workspace_bytes",
+    "shear_forward",
+    "shear_inverse",
+    "shear_adjoint",
+    "shear_profile_enable",
+    "shear_profile_read",
+    "shear_destroy_system",
+    "shear_strerror",
+    "shear_last_error",
+)
+
+
+class ShearError(RuntimeError):
+    """A negative status returned by libshear."""
+
+    def __init__(self, code: int, where: str, detail: str):
+        self.code = code
+        self.name = ERRORS.get(code, "UNKNOWN")
+        super().__init__(f"{where}: {self.name} ({code}): {detail}")
+
+
+class BuildParams(ctypes.Structure):
+    _fields_ = [
+        ("rows", ctypes.c_int),
+        ("cols", ctypes.c_int),
+        ("n_scales", ctypes.c_int),
+        ("shear_levels", ctypes.POINTER(ctypes.c_int)),
+        ("scaling_taps", ctypes.POINTER(ctypes.c_double)),
+        ("n_scaling", ctypes.c_int),
+        ("fan_taps", ctypes.POINTER(ctypes.c_double)),
+        ("fan_rows", ctypes.c_int),
+        ("fan_cols", ctypes.c_int),
+        ("max_workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads libshear.so once and declares the C signatures. Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() (hipcc --offload-arch=gfx950)")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    pI = ctypes.POINTER(ctypes.c_int)
+    pD = ctypes.POINTER(ctypes.c_double)
+    lib.shear_design_spectra.argtypes = [ctypes.POINTER(BuildParams), pI, pD, pI]
+    lib.shear_build_system.argtypes = [ctypes.POINTER(BuildParams), ctypes.POINTER(P)]
+    lib.shear_system_from_spectra.argtypes = [I, I, I, pD, pI, ctypes.c_size_t, ctypes.POINTER(P)]
+    lib.shear_system_info.argtypes = [P, pI, pI, pI, pD, pI]
+    lib.shear_export_spectra.argtypes = [P, pD, pD]
+    lib.shear_reserve.argtypes = [P, I]
+    lib.shear_workspace_bytes.argtypes = [P, I, ctypes.POINTER(ctypes.c_size_t)]
+    for name in ("shear_forward", "shear_inverse", "shear_adjoint"):
+        getattr(lib, name).argtypes = [P, P, P, I, P]
+    for name in EXPORTED:
+        if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
+            getattr(lib, name).restype = I
+    lib.shear_profile_enable.argtypes = [P, I]
+    lib.shear_profile_read.argtypes = [P, pI, pD]
+    lib.shear_destroy_system.argtypes = [P]
+    lib.shear_destroy_system.restype = None
+    lib.shear_strerror.argtypes = [I]
+    lib.shear_strerror.restype = ctypes.c_char_p
+    lib.shear_last_error.argtypes = []
+    lib.shear_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != SHEAR_OK:
+        detail = load_library().shear_last_error().decode(errors="replace")
+        raise ShearError(rc, where, detail)
+
+
+def _params(rows, cols, n_scales, shear_levels, scaling_taps, fan_taps, max_workspace_bytes, keep: list) -> BuildParams:
+    p = BuildParams()
+    p.rows, p.cols, p.n_scales = int(rows), int(cols), int(n_scales)
+    if shear_levels is not None:
+        arr = (ctypes.c_int * len(shear_levels))(*[int(v) for v in shear_levels])
+        keep.append(arr)
+        p.shear_levels = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+    if scaling_taps is not None:
+        h = np.ascontiguousarray(scaling_taps, dtype=np.float64)
+        keep.append(h)
+        p.scaling_taps = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.n_scaling = h.size
+    if fan_taps is not None:
+        f = np.ascontiguousarray(fan_taps, dtype=np.float64)
+        keep.append(f)
+        p.fan_taps = f.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        p.fan_rows, p.fan_cols = f.shape
+    p.max_workspace_bytes = int(max_workspace_bytes)
+    return p
+
+
+def design_spectra(rows: int, cols: int, n_scales: int, shear_levels: Optional[Sequence[int]] = None,
+                   scaling_taps=None, fan_taps=None):
+    """Host-only filter design (shear_design_spectra). Returns (spectra_centred complex128 (K,rows,cols), idx (K,3))."""
+    lib = load_library()
+    keep: list = []
+    p = _params(rows, cols, n_scales, shear_levels, scaling_taps, fan_taps, 0, keep)
+    K = ctypes.c_int(0)
+    _check(lib.shear_design_spectra(ctypes.byref(p), ctypes.byref(K), None, None), "shear_design_spectra")
+    spec = np.zeros((K.value, rows, cols, 2), dtype=np.float64)
+    idx = np.zeros((K.value, 3), dtype=np.int32)
+    _check(lib.shear_design_spectra(ctypes.byref(p), ctypes.byref(K),
+                                    spec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), "shear_design_spectra")
+    return spec[..., 0] + 1j * spec[..., 1], idx
+
+
+def _stream_ptr(stream) -> ctypes.c_void_p:
+    import torch
+
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+class ShearletSystem:
+    """A shearlet system on the current GPU (shear_build_system / shear_system_from_spectra)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        self._lib = load_library()
+        K, r, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.shear_system_info(self._h, ctypes.byref(K), ctypes.byref(r), ctypes.byref(c), None, None),
+               "shear_system_info")
+        self.K, self.rows, self.cols = K.value, r.value, c.value
+
+    # ------------------------------------------------------------ construction
+    @classmethod
+    def build(cls, rows: int, cols: int, n_scales: int, shear_levels: Optional[Sequence[int]] = None,
+              scaling_taps=None, fan_taps=None, max_workspace_bytes: int = 0) -> "ShearletSystem":
+        lib = load_library()
+        keep: list = []
+        p = _params(rows, cols, n_scales, shear_levels, scaling_taps, fan_taps, max_workspace_bytes, keep)
+        h = ctypes.c_void_p()
+        _check(lib.shear_build_system(ctypes.byref(p), ctypes.byref(h)), "shear_build_system")
+        return cls(h)
+
+    @classmethod
+    def from_spectra(cls, spectra_centred, idx=None, max_workspace_bytes: int = 0) -> "ShearletSystem":
+        lib = load_library()
+        S = np.asarray(spectra_centred)
+        K, rows, cols = S.shape
+        buf = np.ascontiguousarray(np.stack([S.real, S.imag], axis=-1), dtype=np.float64)
+        pidx = None
+        if idx is not None:
+            iv = np.ascontiguousarray(idx, dtype=np.int32)
+            pidx = iv.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        h = ctypes.c_void_p()
+        _check(lib.shear_system_from_spectra(rows, cols, K, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), pidx,
+                                             int(max_workspace_bytes), ctypes.byref(h)), "shear_system_from_spectra")
+        return cls(h)
+
+    # ------------------------------------------------------------ info
+    @property
+    def rms(self) -> np.ndarray:
+        out = np.zeros(self.K, dtype=np.float64)
+        _check(self._lib.shear_system_info(self._h, None, None, None, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           None), "shear_system_info")
+        return out
+
+    @property
+    def idx(self) -> np.ndarray:
+        out = np.zeros((self.K, 3), dtype=np.int32)
+        _check(self._lib.shear_system_info(self._h, None, None, None, None,
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), "shear_system_info")
+        return out
+
+    def export_spectra(self):
+        """(spectra_centred complex128 (K, rows, cols), W_centred float64 (rows, cols))."""
+        spec = np.zeros((self.K, self.rows, self.cols, 2), dtype=np.float64)
+        W = np.zeros((self.rows, self.cols), dtype=np.float64)
+        _check(self._lib.shear_export_spectra(self._h, spec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              W.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "shear_export_spectra")
+        return spec[..., 0] + 1j * spec[..., 1], W
+
+    def reserve(self, batch: int) -> None:
+        _check(self._lib.shear_reserve(self._h, int(batch)), "shear_reserve")
+
+    def workspace_bytes(self, batch: int) -> int:
+        b = ctypes.c_size_t()
+        _check(self._lib.shear_workspace_bytes(self._h, int(batch), ctypes.byref(b)), "shear_workspace_bytes")
+        return b.value
+
+    # ------------------------------------------------------------ transforms
+    def _check_tensor(self, t, shape, name):
+        import torch
+
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+    def forward(self, x, out=None, stream=None):
+        """shear_forward: x (B, rows, cols) -> coefficients (B, K, rows, cols)."""
+        import torch
+
+        B = x.shape[0]
+        self._check_tensor(x, (B, self.rows, self.cols), "x")
+        if out is None:
+            out = torch.empty((B, self.K, self.rows, self.cols), dtype=torch.float32, device=x.device)
+        self._check_tensor(out, (B, self.K, self.rows, self.cols), "out")
+        _check(self._lib.shear_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
+                                       _stream_ptr(stream)), "shear_forward")
+        return out
+
+    def _inv(self, fn, name, c, out, stream):
+        import torch
+
+        B = c.shape[0]
+        self._check_tensor(c, (B, self.K, self.rows, self.cols), "coeffs")
+        if out is None:
+            out = torch.empty((B, self.rows, self.cols), dtype=torch.float32, device=c.device)
+        self._check_tensor(out, (B, self.rows, self.cols), "out")
+        _check(fn(self._h, ctypes.c_void_p(c.data_ptr()), ctypes.c_void_p(out.data_ptr()), B, _stream_ptr(stream)), name)
+        return out
+
+    def inverse(self, coeffs, out=None, stream=None):
+        """shear_inverse: coefficients (B, K, rows, cols) -> images (B, rows, cols)."""
+        return self._inv(self._lib.shear_inverse, "shear_inverse", coeffs, out, stream)
+
+    def adjoint(self, coeffs, out=None, stream=None):
+        """shear_adjoint: coefficients (B, K, rows, cols) -> images (B, rows, cols)."""
+        return self._inv(self._lib.shear_adjoint, "shear_adjoint", coeffs, out, stream)
+
+    # ------------------------------------------------------------ tracing
+    KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images")
+
+    def profile(self, on: bool = True) -> None:
+        """Brackets every launch with hipEvents on the caller's stream (shear_profile_enable)."""
+        _check(self._lib.shear_profile_enable(self._h, 1 if on else 0), "shear_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kind: (launches, total_ms)} since the last read (shear_profile_read); waits for the events."""
+        n = (ctypes.c_int * 6)()
+        ms = (ctypes.c_double * 6)()
+        _check(self._lib.shear_profile_read(self._h, n, ms), "shear_profile_read")
+        return {k: (n[i], ms[i]) for i, k in enumerate(self.KERNEL_KINDS)}
+
+    # ------------------------------------------------------------ lifetime
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            self._lib.shear_destroy_system(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

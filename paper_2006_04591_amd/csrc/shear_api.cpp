@@ -1,0 +1,577 @@
+// C ABI of the shearlet filter-bank library (declared in include/shear.h).
+//
+// Host side of every call: argument checks, the FP64 -> FP32 preparation of
+// the three device filter sets, workspace management and kernel launches.
+// The device work itself is in kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "builder.h"
+#include "kernels.h"
+#include "shear.h"
+
+using shear::cd;
+
+struct shear_system {
+    int device = -1;
+    int rows = 0, cols = 0, K = 0;
+    bool real = false;
+    std::vector<cd> spectra;   // K x rows x cols, natural order
+    std::vector<double> W;     // rows x cols, natural order
+    std::vector<double> rms;   // K
+    std::vector<int> idx;      // K x 3
+    // device
+    void* dev_block = nullptr;  // twiddles + three filter sets
+    const void* filt_fwd = nullptr;
+    const void* filt_inv = nullptr;
+    const void* filt_adj = nullptr;
+    shear::DevPlan plan;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t ws_cap = 0;
+    // per-launch timing (shear_profile_enable / shear_profile_read)
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_free;
+    struct Rec {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> prof;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SHEAR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t centred_to_natural(size_t i, int n) { return (i + (size_t)n / 2) % (size_t)n; }
+
+// Natural-order index (r, c) of the centred-layout element (rc, cc): the
+// centred layout is fftshift(natural), so centred[rc] = natural[(rc + n/2) mod n]
+// for even n (the only sizes accepted).
+void centred_to_natural_spectra(const double* in, int K, int rows, int cols, std::vector<cd>& out) {
+    out.assign((size_t)K * rows * cols, cd(0, 0));
+    for (int k = 0; k < K; ++k)
+        for (int r = 0; r < rows; ++r)
+            for (int c = 0; c < cols; ++c) {
+                const double* e = in + (((size_t)k * rows + r) * cols + c) * 2;
+                out[((size_t)k * rows + centred_to_natural(r, rows)) * cols + centred_to_natural(c, cols)] = cd(e[0], e[1]);
+            }
+}
+
+void natural_to_centred(const cd* in, int rows, int cols, double* out2 /* (re,im) */, double* outr /* real */) {
+    for (int r = 0; r < rows; ++r)
+        for (int c = 0; c < cols; ++c) {
+            const cd v = in[(size_t)centred_to_natural(r, rows) * cols + centred_to_natural(c, cols)];
+            const size_t o = (size_t)r * cols + c;
+            if (out2) {
+                out2[2 * o] = v.real();
+                out2[2 * o + 1] = v.imag();
+            }
+            if (outr) outr[o] = v.real();
+        }
+}
+
+// Device filter set layout: [k][col in 0..L][row in 0..N-1], float or float2.
+//   columns 1..L-1 : the filter value at (row, col);
+//   column 0       : (f(row, 0) + f(row, M/2)) / 2           -- acts on the packed DC/Nyquist column
+//   column L       : forward: (f(row, 0) - f(row, M/2)) / 2,  multiplies conj(X(-row))
+//                    inverse: conj of that at row -row,       accumulated then mirrored once
+// where f = conj(Psi) (forward) or the dual / adjoint filter Psi * wgt (inverse side).
+void pack_filter_set(const shear_system& s, bool forward, const std::vector<double>& wgt, std::vector<float>& out) {
+    const int N = s.rows, M = s.cols, L = M / 2, K = s.K;
+    const size_t per = (size_t)(L + 1) * N;
+    const int comps = s.real ? 1 : 2;
+    out.assign((size_t)K * per * comps, 0.0f);
+    auto put = [&](int k, int col, int row, cd v) {
+        const size_t i = (size_t)k * per + (size_t)col * N + row;
+        if (s.real) {
+            out[i] = (float)v.real();
+        } else {
+            out[2 * i] = (float)v.real();
+            out[2 * i + 1] = (float)v.imag();
+        }
+    };
+    for (int k = 0; k < K; ++k) {
+        const cd* P = s.spectra.data() + (size_t)k * N * M;
+        auto f = [&](int row, int col) -> cd {
+            const cd v = P[(size_t)row * M + col];
+            return forward ? std::conj(v) : v * wgt[(size_t)row * M + col];
+        };
+        for (int row = 0; row < N; ++row) {
+            for (int col = 1; col < L; ++col) put(k, col, row, f(row, col));
+            put(k, 0, row, 0.5 * (f(row, 0) + f(row, L)));
+            if (forward) {
+                put(k, L, row, 0.5 * (f(row, 0) - f(row, L)));
+            } else {
+                const int mr = (N - row) % N;
+                put(k, L, row, std::conj(0.5 * (f(mr, 0) - f(mr, L))));
+            }
+        }
+    }
+}
+
+int finish_system(shear_system* s, std::string& why) {
+    const int N = s->rows, M = s->cols, K = s->K;
+    const size_t NM = (size_t)N * M;
+    s->W.assign(NM, 0.0);
+    s->rms.assign((size_t)K, 0.0);
+    for (int k = 0; k < K; ++k) {
+        double e = 0.0;
+        for (size_t i = 0; i < NM; ++i) {
+            const double a = std::norm(s->spectra[(size_t)k * NM + i]);
+            s->W[i] += a;
+            e += a;
+        }
+        s->rms[(size_t)k] = std::sqrt(e / (double)NM);
+    }
+    const double wmin = *std::min_element(s->W.begin(), s->W.end());
+    const double wmax = *std::max_element(s->W.begin(), s->W.end());
+    if (!(wmin > 1e-10 * wmax)) {
+        why = "dual-frame weight is (nearly) zero: min W = " + std::to_string(wmin) + ", max W = " + std::to_string(wmax);
+        return SHEAR_E_FRAME;
+    }
+    // filter sets (FP64 -> FP32 once)
+    std::vector<double> winv(NM), wadj(NM, 1.0 / (double)NM);
+    for (size_t i = 0; i < NM; ++i) winv[i] = 1.0 / (s->W[i] * (double)NM);
+    std::vector<float> ffwd, finv, fadj;
+    pack_filter_set(*s, true, wadj, ffwd);
+    pack_filter_set(*s, false, winv, finv);
+    pack_filter_set(*s, false, wadj, fadj);
+    // twiddles exp(-2 pi i m / n), computed in FP64 and rounded once
+    const int L = M / 2;
+    std::vector<float> tw;
+    auto add_tw = [&](int n) {
+        size_t off = tw.size();
+        for (int m = 0; m < n; ++m) {
+            const double a = -2.0 * M_PI * (double)m / (double)n;
+            tw.push_back((float)std::cos(a));
+            tw.push_back((float)std::sin(a));
+        }
+        return off;
+    };
+    const size_t oN = add_tw(N), oL = add_tw(L), oM = add_tw(M);
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_tw = al(tw.size() * sizeof(float));
+    const size_t b_f = al(ffwd.size() * sizeof(float));
+    const size_t total = b_tw + 3 * b_f;
+    hipError_t e = hipMalloc(&s->dev_block, total);
+    if (e != hipSuccess) {
+        s->dev_block = nullptr;
+        why = std::string("hipMalloc of the filter bank failed: ") + hipGetErrorString(e);
+        return SHEAR_E_NOMEM;
+    }
+    char* base = (char*)s->dev_block;
+    if ((e = hipMemcpy(base, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(base + b_tw, ffwd.data(), ffwd.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(base + b_tw + b_f, finv.data(), finv.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(base + b_tw + 2 * b_f, fadj.data(), fadj.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+            hipSuccess) {
+        why = std::string("hipMemcpy of the filter bank failed: ") + hipGetErrorString(e);
+        return SHEAR_E_HIP;
+    }
+    const float2* twb = (const float2*)base;
+    s->plan.N = N;
+    s->plan.M = M;
+    s->plan.L = L;
+    s->plan.K = K;
+    s->plan.real = s->real;
+    s->plan.twN = twb + oN / 2;
+    s->plan.twL = twb + oL / 2;
+    s->plan.twM = twb + oM / 2;
+    s->filt_fwd = base + b_tw;
+    s->filt_inv = base + b_tw + b_f;
+    s->filt_adj = base + b_tw + 2 * b_f;
+    return SHEAR_OK;
+}
+
+void release(shear_system* s) {
+    if (!s) return;
+    for (auto& r : s->prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
+    if (s->dev_block) (void)hipFree(s->dev_block);
+    if (s->ws) (void)hipFree(s->ws);
+    delete s;
+}
+
+int new_system(int rows, int cols, size_t cap, shear_system** out, shear_system*& s) {
+    if (!out) return fail(SHEAR_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!shear::size_supported(rows) || !shear::size_supported(cols))
+        return fail(SHEAR_E_SIZE, "GPU path needs rows and cols powers of two in [16, 1024], got " + std::to_string(rows) +
+                                      "x" + std::to_string(cols));
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    s = new (std::nothrow) shear_system();
+    if (!s) return fail(SHEAR_E_NOMEM, "host allocation failed");
+    s->device = dev;
+    s->rows = rows;
+    s->cols = cols;
+    s->ws_cap = cap ? cap : ((size_t)4 << 30);
+    return SHEAR_OK;
+}
+
+size_t plane_bytes(const shear_system* s) { return (size_t)s->rows * (s->cols / 2) * sizeof(float2); }
+
+// Images per chunk of the K-expanded intermediate, or 0 if even one does not fit.
+int chunk_images(const shear_system* s, int batch) {
+    const size_t pb = plane_bytes(s);
+    const size_t fixed = (size_t)batch * pb;
+    if (fixed >= s->ws_cap) return 0;
+    const size_t per = (size_t)s->K * pb;
+    const size_t n = (s->ws_cap - fixed) / per;
+    return (int)std::min<size_t>(n, (size_t)batch);
+}
+
+size_t ws_needed(const shear_system* s, int batch, int chunk) {
+    return (size_t)batch * plane_bytes(s) + (size_t)chunk * s->K * plane_bytes(s);
+}
+
+int ensure_ws(shear_system* s, size_t bytes) {
+    if (bytes <= s->ws_bytes) return SHEAR_OK;
+    if (s->ws) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before workspace growth");
+        (void)hipFree(s->ws);
+        s->ws = nullptr;
+        s->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s->ws, bytes);
+    if (e != hipSuccess) {
+        s->ws = nullptr;
+        return fail(SHEAR_E_NOMEM, std::string("workspace hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    s->ws_bytes = bytes;
+    return SHEAR_OK;
+}
+
+int check_call(shear_system* s, const void* a, const void* b, int batch) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    if (!a || !b) return fail(SHEAR_E_INVALID, "input or output pointer is NULL");
+    if (batch <= 0) return fail(SHEAR_E_INVALID, "batch must be positive");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != s->device)
+        return fail(SHEAR_E_DEVICE, "current device " + std::to_string(dev) + " is not the system's device " +
+                                        std::to_string(s->device));
+    return SHEAR_OK;
+}
+
+int prepare_ws(shear_system* s, int batch, int& chunk) {
+    chunk = chunk_images(s, batch);
+    if (chunk < 1)
+        return fail(SHEAR_E_NOMEM, "workspace cap of " + std::to_string(s->ws_cap) + " bytes is below the " +
+                                       std::to_string(ws_needed(s, batch, 1)) + " bytes one image needs");
+    return ensure_ws(s, ws_needed(s, batch, chunk));
+}
+
+hipError_t take_event(shear_system* s, hipEvent_t& e) {
+    if (!s->ev_free.empty()) {
+        e = s->ev_free.back();
+        s->ev_free.pop_back();
+        return hipSuccess;
+    }
+    return hipEventCreate(&e);
+}
+
+// Runs one launch; with profiling on, brackets it with two events on the same stream.
+template <typename F>
+hipError_t timed(shear_system* s, int kind, hipStream_t st, F&& launch) {
+    if (!s->prof_on) return launch();
+    hipEvent_t a, b;
+    hipError_t e = take_event(s, a);
+    if (e != hipSuccess) return e;
+    if ((e = take_event(s, b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(a, st)) != hipSuccess) return e;
+    if ((e = launch()) != hipSuccess) return e;
+    if ((e = hipEventRecord(b, st)) != hipSuccess) return e;
+    s->prof.push_back({kind, a, b});
+    return hipSuccess;
+}
+
+int inverse_like(shear_system* s, const float* coeffs, float* x, int batch, void* stream, const void* filt) {
+    int rc = check_call(s, coeffs, x, batch);
+    if (rc != SHEAR_OK) return rc;
+    int chunk = 0;
+    if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
+    const shear::DevPlan& d = s->plan;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t pb = plane_bytes(s) / sizeof(float2);
+    float2* V = (float2*)s->ws;
+    float2* U = V + (size_t)batch * pb;
+    const size_t img = (size_t)d.N * d.M;
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
+        hipError_t e = timed(s, SHEAR_KERNEL_ROWS_R2C_COEFFS, st, [&] {
+            return shear::launch_rows_r2c(d, coeffs + (size_t)b0 * d.K * img, U, nb * d.K, true, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "row r2c launch");
+        e = timed(s, SHEAR_KERNEL_COLS_INV, st,
+                  [&] { return shear::launch_cols_inv(d, U, V + (size_t)b0 * pb, nb, filt, st); });
+        if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    }
+    hipError_t e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
+                         [&] { return shear::launch_rows_c2r(d, V, x, batch, 1.0f, false, st); });
+    if (e != hipSuccess) return hip_fail(e, "row c2r launch");
+    return SHEAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* shear_strerror(int code) {
+    switch (code) {
+        case SHEAR_OK: return "ok";
+        case SHEAR_E_INVALID: return "invalid argument";
+        case SHEAR_E_SIZE: return "unsupported size";
+        case SHEAR_E_FRAME: return "not a usable frame (zero dual-frame weight or non-Hermitian spectra)";
+        case SHEAR_E_NOMEM: return "out of memory";
+        case SHEAR_E_HIP: return "HIP error";
+        case SHEAR_E_DEVICE: return "wrong device";
+    }
+    return "unknown error";
+}
+
+const char* shear_last_error(void) { return g_err.c_str(); }
+
+int shear_design_spectra(const shear_build_params* p, int* K, double* spectra_centred, int* idx) {
+    try {
+        if (!K) return fail(SHEAR_E_INVALID, "K is NULL");
+        std::string why;
+        if (!spectra_centred && !idx) {
+            int rc = shear::count_filters(p, *K, why);
+            return rc == SHEAR_OK ? SHEAR_OK : fail(rc, why);
+        }
+        shear::Design d;
+        int rc = shear::design(p, d, why);
+        if (rc != SHEAR_OK) return fail(rc, why);
+        *K = d.K;
+        if (spectra_centred)
+            for (int k = 0; k < d.K; ++k)
+                natural_to_centred(d.spectra.data() + (size_t)k * d.rows * d.cols, d.rows, d.cols,
+                                   spectra_centred + (size_t)k * d.rows * d.cols * 2, nullptr);
+        if (idx) std::memcpy(idx, d.idx.data(), sizeof(int) * d.idx.size());
+        return SHEAR_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(SHEAR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(SHEAR_E_INVALID, "unexpected failure in shear_design_spectra");
+    }
+}
+
+int shear_build_system(const shear_build_params* p, shear_system** out) {
+    shear_system* s = nullptr;
+    try {
+        if (!p) return fail(SHEAR_E_INVALID, "params is NULL");
+        int rc = new_system(p->rows, p->cols, p->max_workspace_bytes, out, s);
+        if (rc != SHEAR_OK) return rc;
+        shear::Design d;
+        std::string why;
+        rc = shear::design(p, d, why);
+        if (rc != SHEAR_OK) {
+            release(s);
+            return fail(rc, why);
+        }
+        s->K = d.K;
+        s->real = d.real;
+        s->spectra = std::move(d.spectra);
+        s->idx = std::move(d.idx);
+        rc = finish_system(s, why);
+        if (rc != SHEAR_OK) {
+            release(s);
+            return fail(rc, why);
+        }
+        *out = s;
+        return SHEAR_OK;
+    } catch (const std::bad_alloc&) {
+        release(s);
+        return fail(SHEAR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        release(s);
+        return fail(SHEAR_E_INVALID, "unexpected failure in shear_build_system");
+    }
+}
+
+int shear_system_from_spectra(int rows, int cols, int K, const double* spectra_centred, const int* idx,
+                              size_t max_workspace_bytes, shear_system** out) {
+    shear_system* s = nullptr;
+    try {
+        if (!spectra_centred) return fail(SHEAR_E_INVALID, "spectra is NULL");
+        if (K <= 0) return fail(SHEAR_E_INVALID, "K must be positive");
+        int rc = new_system(rows, cols, max_workspace_bytes, out, s);
+        if (rc != SHEAR_OK) return rc;
+        s->K = K;
+        centred_to_natural_spectra(spectra_centred, K, rows, cols, s->spectra);
+        const size_t NM = (size_t)rows * cols;
+        double amax = 0.0, herm = 0.0, imax = 0.0;
+        for (int k = 0; k < K; ++k) {
+            const cd* P = s->spectra.data() + (size_t)k * NM;
+            for (int r = 0; r < rows; ++r)
+                for (int c = 0; c < cols; ++c) {
+                    const cd v = P[(size_t)r * cols + c];
+                    const cd m = P[(size_t)((rows - r) % rows) * cols + (size_t)((cols - c) % cols)];
+                    amax = std::max(amax, std::abs(v));
+                    imax = std::max(imax, std::fabs(v.imag()));
+                    herm = std::max(herm, std::abs(v - std::conj(m)));
+                }
+        }
+        if (herm > 1e-9 * amax) {
+            release(s);
+            return fail(SHEAR_E_FRAME, "spectra are not Hermitian (coefficients would not be real): deviation " +
+                                           std::to_string(herm) + " vs max " + std::to_string(amax));
+        }
+        s->real = imax <= 1e-12 * amax;
+        if (s->real)
+            for (cd& v : s->spectra) v = cd(v.real(), 0.0);
+        s->idx.assign((size_t)K * 3, 0);
+        for (int k = 0; k < K; ++k) {
+            if (idx) {
+                for (int j = 0; j < 3; ++j) s->idx[(size_t)k * 3 + j] = idx[(size_t)k * 3 + j];
+            } else {
+                s->idx[(size_t)k * 3 + 2] = k;
+            }
+        }
+        std::string why;
+        rc = finish_system(s, why);
+        if (rc != SHEAR_OK) {
+            release(s);
+            return fail(rc, why);
+        }
+        *out = s;
+        return SHEAR_OK;
+    } catch (const std::bad_alloc&) {
+        release(s);
+        return fail(SHEAR_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        release(s);
+        return fail(SHEAR_E_INVALID, "unexpected failure in shear_system_from_spectra");
+    }
+}
+
+int shear_system_info(const shear_system* s, int* K, int* rows, int* cols, double* rms, int* idx) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    if (K) *K = s->K;
+    if (rows) *rows = s->rows;
+    if (cols) *cols = s->cols;
+    if (rms) std::memcpy(rms, s->rms.data(), sizeof(double) * s->rms.size());
+    if (idx) std::memcpy(idx, s->idx.data(), sizeof(int) * s->idx.size());
+    return SHEAR_OK;
+}
+
+int shear_export_spectra(const shear_system* s, double* spectra_centred, double* W_centred) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    const size_t NM = (size_t)s->rows * s->cols;
+    if (spectra_centred)
+        for (int k = 0; k < s->K; ++k)
+            natural_to_centred(s->spectra.data() + (size_t)k * NM, s->rows, s->cols, spectra_centred + (size_t)k * NM * 2,
+                               nullptr);
+    if (W_centred) {
+        std::vector<cd> w(s->W.begin(), s->W.end());
+        natural_to_centred(w.data(), s->rows, s->cols, nullptr, W_centred);
+    }
+    return SHEAR_OK;
+}
+
+int shear_workspace_bytes(const shear_system* s, int batch, size_t* bytes) {
+    if (!s || !bytes) return fail(SHEAR_E_INVALID, "NULL argument");
+    if (batch <= 0) return fail(SHEAR_E_INVALID, "batch must be positive");
+    const int chunk = chunk_images(s, batch);
+    if (chunk < 1) return fail(SHEAR_E_NOMEM, "workspace cap too small for one image");
+    *bytes = ws_needed(s, batch, chunk);
+    return SHEAR_OK;
+}
+
+int shear_reserve(shear_system* s, int batch) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    if (batch <= 0) return fail(SHEAR_E_INVALID, "batch must be positive");
+    int chunk = 0;
+    return prepare_ws(s, batch, chunk);
+}
+
+int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, void* stream) {
+    int rc = check_call(s, x, coeffs, batch);
+    if (rc != SHEAR_OK) return rc;
+    int chunk = 0;
+    if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
+    const shear::DevPlan& d = s->plan;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t pb = plane_bytes(s) / sizeof(float2);
+    float2* A = (float2*)s->ws;
+    float2* T = A + (size_t)batch * pb;
+    const size_t img = (size_t)d.N * d.M;
+    hipError_t e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st,
+                         [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
+    if (e != hipSuccess) return hip_fail(e, "row r2c launch");
+    const float scale = (float)(1.0 / (double)img);  // 1/(N M): a power of two, exact
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
+        e = timed(s, SHEAR_KERNEL_COLS_FWD, st,
+                  [&] { return shear::launch_cols_fwd(d, A + (size_t)b0 * pb, T, nb, s->filt_fwd, scale, st); });
+        if (e != hipSuccess) return hip_fail(e, "column pass launch");
+        e = timed(s, SHEAR_KERNEL_ROWS_C2R_COEFFS, st, [&] {
+            return shear::launch_rows_c2r(d, T, coeffs + (size_t)b0 * d.K * img, nb * d.K, 1.0f, true, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "row c2r launch");
+    }
+    return SHEAR_OK;
+}
+
+int shear_inverse(shear_system* s, const float* coeffs, float* x, int batch, void* stream) {
+    return inverse_like(s, coeffs, x, batch, stream, s ? s->filt_inv : nullptr);
+}
+
+int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, void* stream) {
+    return inverse_like(s, coeffs, x, batch, stream, s ? s->filt_adj : nullptr);
+}
+
+int shear_profile_enable(shear_system* s, int on) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    s->prof_on = on != 0;
+    return SHEAR_OK;
+}
+
+int shear_profile_read(shear_system* s, int* launches, double* total_ms) {
+    if (!s || !launches || !total_ms) return fail(SHEAR_E_INVALID, "NULL argument");
+    for (int k = 0; k < SHEAR_KERNEL_KINDS; ++k) {
+        launches[k] = 0;
+        total_ms[k] = 0.0;
+    }
+    int rc = SHEAR_OK;
+    for (auto& r : s->prof) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess && rc == SHEAR_OK) rc = hip_fail(e, "reading launch events");
+        launches[r.kind] += 1;
+        total_ms[r.kind] += ms;
+        s->ev_free.push_back(r.a);
+        s->ev_free.push_back(r.b);
+    }
+    s->prof.clear();
+    return rc;
+}
+
+void shear_destroy_system(shear_system* s) { release(s); }
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Inputs are seeded and shared (synth); the oracle never sees a GPU output.
+Bar: relative L2 error <= 1e-5 (FP32 path vs FP64 oracle), also per plane
+normalised by ||x|| * RMS_k.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import filters as OF
+from oracle import transform as OT
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2006_04591_amd import load_library
+
+    return load_library()
+
+
+def _to(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+# ---------------------------------------------------------------- 128x128, 17 filters (one image, FP64 workload at FP32)
+
+
+@pytest.fixture(scope="module")
+def cfg1(gpu, lib):
+    from paper_2006_04591_amd import ShearletSystem
+
+    _say("case: build 128x128 J=2 (K=17)")
+    s = ShearletSystem.build(128, 128, 2)
+    ref = OF.build_system(128, 128, 2)
+    x = synth.cartoon(128, 128, synth.seed_image(1, 0))
+    yield s, ref, x
+    s.close()
+
+
+def test_system_matches_oracle_spectra(cfg1):
+    s, ref, _ = cfg1
+    S, W = s.export_spectra()
+    assert np.max(np.abs(S - ref.centred)) <= 1e-12 * np.max(np.abs(ref.centred))
+    assert np.max(np.abs(W - np.fft.fftshift(ref.W))) <= 1e-12 * ref.W.max()
+    assert np.allclose(s.rms, ref.rms, rtol=1e-12)
+    assert np.array_equal(s.idx, ref.idx)
+
+
+def test_forward_config1(cfg1, gpu):
+    s, ref, x = cfg1
+    _say("case: forward 128x128 K=17 B=1")
+    c = s.forward(_to(x[None], gpu))
+    torch.cuda.synchronize()
+    got = c[0].double().cpu().numpy()
+    want = OT.forward_plain(x.astype(np.float64), ref.spectra)
+    assert _rel(got, want) <= TOL
+    nx = np.linalg.norm(x.astype(np.float64))
+    per = [np.linalg.norm(got[k] - want[k]) / (nx * ref.rms[k]) for k in range(ref.K)]
+    assert max(per) <= TOL
+
+
+def test_inverse_and_adjoint_config1(cfg1, gpu):
+    s, ref, x = cfg1
+    c_in = OT.forward_plain(x.astype(np.float64), ref.spectra).astype(np.float32)
+    _say("case: inverse/adjoint 128x128 K=17 B=1")
+    cg = _to(c_in[None], gpu)
+    y = s.inverse(cg)
+    a = s.adjoint(cg)
+    torch.cuda.synchronize()
+    cb = c_in.astype(np.float64)
+    assert _rel(y[0].cpu().numpy(), OT.inverse_plain(cb, ref.spectra, ref.W)) <= TOL
+    assert _rel(a[0].cpu().numpy(), OT.adjoint_plain(cb, ref.spectra)) <= TOL
+
+
+def test_adjoint_random_coefficients(cfg1, gpu):
+    s, ref, _ = cfg1
+    rng = np.random.default_rng(11)
+    c_in = rng.standard_normal((2, ref.K, 128, 128)).astype(np.float32)
+    _say("case: adjoint 128x128 K=17 B=2 random coefficients")
+    a = s.adjoint(_to(c_in, gpu))
+    torch.cuda.synchronize()
+    for b in range(2):
+        assert _rel(a[b].cpu().numpy(), OT.adjoint_plain(c_in[b].astype(np.float64), ref.spectra)) <= TOL
+
+
+def test_perfect_reconstruction_gpu(cfg1, gpu):
+    s, _, x = cfg1
+    _say("case: PR chain 128x128 K=17")
+    xg = _to(x[None], gpu)
+    y = s.inverse(s.forward(xg))
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), x[None]) <= TOL
+
+
+def test_deterministic(cfg1, gpu):
+    s, _, x = cfg1
+    _say("case: determinism 128x128")
+    xg = _to(np.stack([x, x[::-1].copy()]), gpu)
+    a = s.forward(xg).clone()
+    b = s.forward(xg)
+    ya = s.inverse(a).clone()
+    yb = s.inverse(b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(ya, yb)
+
+
+# ---------------------------------------------------------------- small and ragged shapes, user filter banks
+
+
+def _random_bank(rng, K, N, M, real):
+    ker = rng.standard_normal((K, N, M))
+    if real:  # centro-symmetric kernels -> real spectra
+        ker = ker + ker[:, (-np.arange(N)) % N][:, :, (-np.arange(M)) % M]
+    S = np.fft.fft2(ker)
+    return S
+
+
+@pytest.mark.parametrize("N,M,K,real,B", [(16, 16, 3, False, 1), (32, 64, 5, True, 3), (64, 16, 4, False, 2),
+                                          (128, 32, 7, True, 5), (16, 1024, 2, False, 1), (1024, 16, 2, True, 1)])
+def test_user_bank_shapes(gpu, lib, N, M, K, real, B):
+    from paper_2006_04591_amd import ShearletSystem
+
+    rng = np.random.default_rng(N * 7 + M + K)
+    S = _random_bank(rng, K, N, M, real)
+    W = np.sum(np.abs(S) ** 2, 0)
+    x = rng.standard_normal((B, N, M)).astype(np.float32)
+    c_in = rng.standard_normal((B, K, N, M)).astype(np.float32)
+    _say(f"case: user bank N={N} M={M} K={K} real={real} B={B}")
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        c = s.forward(_to(x, gpu))
+        cg = _to(c_in, gpu)
+        y = s.inverse(cg)
+        a = s.adjoint(cg)
+        torch.cuda.synchronize()
+        for b in range(B):
+            assert _rel(c[b].cpu().numpy(), OT.forward_plain(x[b].astype(np.float64), S)) <= TOL
+            assert _rel(y[b].cpu().numpy(), OT.inverse_plain(c_in[b].astype(np.float64), S, W)) <= TOL
+            assert _rel(a[b].cpu().numpy(), OT.adjoint_plain(c_in[b].astype(np.float64), S)) <= TOL
+
+
+def test_chunked_equals_unchunked(gpu, lib):
+    from paper_2006_04591_amd import ShearletSystem
+
+    rng = np.random.default_rng(5)
+    N, M, K, B = 64, 128, 6, 5
+    S = _random_bank(rng, K, N, M, True)
+    Sc = np.fft.fftshift(S, axes=(1, 2))
+    x = _to(rng.standard_normal((B, N, M)), gpu)
+    one_image = B * N * (M // 2) * 8 + K * N * (M // 2) * 8
+    _say("case: chunked vs unchunked 64x128 K=6 B=5")
+    with ShearletSystem.from_spectra(Sc) as big, ShearletSystem.from_spectra(Sc, max_workspace_bytes=one_image + 1024) as small:
+        assert small.workspace_bytes(B) == one_image
+        c1 = big.forward(x)
+        c2 = small.forward(x)
+        y1 = big.inverse(c1)
+        y2 = small.inverse(c1)
+        torch.cuda.synchronize()
+        assert torch.equal(c1, c2) and torch.equal(y1, y2)
+
+
+def test_non_default_stream(cfg1, gpu):
+    s, ref, x = cfg1
+    _say("case: forward on a side stream")
+    st = torch.cuda.Stream()
+    xg = _to(x[None], gpu)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st):
+        c = s.forward(xg)
+    st.synchronize()
+    assert _rel(c[0].cpu().numpy(), OT.forward_plain(x.astype(np.float64), ref.spectra)) <= TOL
+
+
+def test_profile_counts(cfg1, gpu):
+    s, _, x = cfg1
+    _say("case: per-launch timing")
+    xg = _to(x[None], gpu)
+    s.profile(True)
+    c = s.forward(xg)
+    s.inverse(c)
+    rec = s.profile_read()
+    s.profile(False)
+    assert rec["rows_r2c_images"][0] == 1 and rec["cols_fwd"][0] == 1 and rec["rows_c2r_coeffs"][0] == 1
+    assert rec["rows_r2c_coeffs"][0] == 1 and rec["cols_inv"][0] == 1 and rec["rows_c2r_images"][0] == 1
+    assert all(v[1] > 0 for v in rec.values())
+
+
+def test_errors(gpu, lib):
+    from paper_2006_04591_amd import ShearError, ShearletSystem
+
+    _say("case: error paths")
+    with pytest.raises(ShearError) as e:
+        ShearletSystem.build(2048, 2048, 4)
+    assert e.value.name == "SHEAR_E_SIZE"
+    with pytest.raises(ShearError) as e:
+        ShearletSystem.build(32, 32, 2)  # kernels do not fit
+    assert e.value.name == "SHEAR_E_SIZE"
+    with pytest.raises(ShearError) as e:
+        ShearletSystem.from_spectra(np.zeros((2, 16, 16), complex))
+    assert e.value.name == "SHEAR_E_FRAME"
+    rng = np.random.default_rng(1)
+    bad = rng.standard_normal((2, 16, 16)) + 1j * rng.standard_normal((2, 16, 16))
+    with pytest.raises(ShearError) as e:
+        ShearletSystem.from_spectra(bad)
+    assert e.value.name == "SHEAR_E_FRAME"
+    S = np.fft.fftshift(np.fft.fft2(rng.standard_normal((2, 16, 16))), axes=(1, 2))
+    with ShearletSystem.from_spectra(S, max_workspace_bytes=1000) as s:
+        with pytest.raises(ShearError) as e:
+            s.forward(_to(np.zeros((1, 16, 16)), gpu))
+        assert e.value.name == "SHEAR_E_NOMEM"
+        with pytest.raises(ValueError):
+            s.forward(_to(np.zeros((1, 16, 8)), gpu))
+
+
+# ---------------------------------------------------------------- full-size workloads, sampled against the oracle
+
+
+def _plane_forward(x64, S_k):
+    return np.real(np.fft.ifft2(np.fft.fft2(x64) * np.conj(S_k)))
+
+
+@pytest.fixture(scope="module")
+def cfg2(gpu, lib):
+    from paper_2006_04591_amd import ShearletSystem
+
+    _say("case: build 512x512 J=4 (K=49)")
+    s = ShearletSystem.build(512, 512, 4)
+    ref = OF.build_system(512, 512, 4)
+    yield s, ref
+    s.close()
+
+
+def test_forward_512_k49_b16_sampled(cfg2, gpu):
+    s, ref = cfg2
+    S, _ = s.export_spectra()
+    assert np.max(np.abs(S - ref.centred)) <= 1e-12 * np.max(np.abs(ref.spectra))
+    x = synth.cartoon_batch(16, 512, 512, config=2, sigma=30.0)
+    _say("case: forward 512x512 K=49 B=16")
+    c = s.forward(_to(x, gpu))
+    torch.cuda.synchronize()
+    for b in (0, 7, 15):
+        x64 = x[b].astype(np.float64)
+        for k in (0, 5, 12, 20, 24, 33, 40, 47, 48):
+            want = _plane_forward(x64, ref.spectra[k])
+            got = c[b, k].double().cpu().numpy()
+            assert np.linalg.norm(got - want) <= TOL * np.linalg.norm(x64) * ref.rms[k], (b, k)
+    # whole-tensor property at full size: perfect reconstruction
+    y = s.inverse(c)
+    torch.cuda.synchronize()
+    assert _rel(y.cpu().numpy(), x) <= TOL
+
+
+def test_inverse_512_k49_b16_sampled(cfg2, gpu):
+    s, ref = cfg2
+    S, W = ref.spectra, ref.W
+    rng = np.random.default_rng(2024)
+    x = synth.cartoon_batch(16, 512, 512, config=2, sigma=30.0)
+    c_in = (30.0 * rng.standard_normal((16, 49, 512, 512))).astype(np.float32)
+    for b in (0, 15):  # structured coefficients of real images for two batch members
+        c_in[b] = OT.forward_plain(x[b].astype(np.float64), S).astype(np.float32)
+    _say("case: inverse/adjoint 512x512 K=49 B=16")
+    cg = _to(c_in, gpu)
+    y = s.inverse(cg)
+    a = s.adjoint(cg)
+    torch.cuda.synchronize()
+    for b in (0, 9, 15):
+        cb = c_in[b].astype(np.float64)
+        assert _rel(y[b].cpu().numpy(), OT.inverse_plain(cb, S, W)) <= TOL, b
+        assert _rel(a[b].cpu().numpy(), OT.adjoint_plain(cb, S)) <= TOL, b
+
+
+def test_config4_256_k33_b32_sampled(gpu, lib):
+    from paper_2006_04591_amd import ShearletSystem
+
+    _say("case: 256x256 K=33 B=32 forward + adjoint")
+    ref = OF.build_system(256, 256, 3)
+    with ShearletSystem.build(256, 256, 3) as s:
+        x = synth.cartoon_batch(32, 256, 256, config=4)
+        rng = np.random.default_rng(4)
+        g = rng.standard_normal((32, 33, 256, 256)).astype(np.float32)
+        c = s.forward(_to(x, gpu))
+        a = s.adjoint(_to(g, gpu))
+        torch.cuda.synchronize()
+        for b in (0, 31):
+            x64 = x[b].astype(np.float64)
+            for k in (0, 16, 32):
+                want = _plane_forward(x64, ref.spectra[k])
+                assert np.linalg.norm(c[b, k].double().cpu().numpy() - want) <= TOL * np.linalg.norm(x64) * ref.rms[k]
+            assert _rel(a[b].cpu().numpy(), OT.adjoint_plain(g[b].astype(np.float64), ref.spectra)) <= TOL
