@@ -36,7 +36,8 @@ def log(msg: str) -> None:
 
 
 def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
-    """Algorithmic bytes of one launch of each kernel kind at this workload (one launch per call, no chunking).
+    """Algorithmic bytes per transform call of each kernel kind at this workload (a call with chunked
+    launches splits these bytes evenly over its launches).
 
     The method must read x and the filter bank and write the coefficients in the
     forward transform, and read the coefficients and the filter bank and write
@@ -53,6 +54,11 @@ def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
         "rows_r2c_coeffs": coef,
         "cols_inv": filt,
         "rows_c2r_images": img,
+        "fused_fwd": filt + coef,
+        "fused_inv": coef + filt,
+        "pipe_fwd": filt + coef,
+        "pipe_inv": coef + filt,
+        "pipe_finish": 0,
     }[kind]
 
 
@@ -80,8 +86,9 @@ def traffic_from_profiles(kind: str, per_launch_units: float):
         return None
 
 
-def cpu_baseline(x_host, n_images: int) -> dict:
-    """The FP64 oracle (numpy, as it stands) on a bounded sample: fwd+inv of n_images images."""
+def cpu_baseline(x_host, min_seconds: float, max_images: int) -> dict:
+    """The FP64 oracle (numpy, as it stands) on a bounded sample of the same workload:
+    fwd+inv of the batch images in order (cycling), until min_seconds have elapsed."""
     import numpy as np
 
     from oracle import filters as OF
@@ -90,19 +97,25 @@ def cpu_baseline(x_host, n_images: int) -> dict:
     log(f"cpu baseline: oracle system build 512x512 J={J}")
     ref = OF.build_system(N, M, J)
     t0 = time.perf_counter()
-    for b in range(n_images):
-        c = OT.forward_plain(x_host[b].astype(np.float64), ref.spectra)
+    n = 0
+    while n < max_images:
+        c = OT.forward_plain(x_host[n % B].astype(np.float64), ref.spectra)
         OT.inverse_plain(c, ref.spectra, ref.W)
-        log(f"cpu baseline: image {b + 1}/{n_images} done")
+        n += 1
+        dt = time.perf_counter() - t0
+        if n % 4 == 0:
+            log(f"cpu baseline: {n} images, {dt:.1f} s")
+        if dt >= min_seconds:
+            break
     dt = time.perf_counter() - t0
-    units = n_images * N * M * ref.K / 1e6
+    units = n * N * M * ref.K / 1e6
     return {
         "value": units / dt,
         "unit": "Mpix·filters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"numpy FP64 oracle, fwd+inv of {n_images} of the 16 images (512x512, 49 filters), "
-                  f"{dt:.1f} s; numpy.fft runs single-threaded",
+        "sample": f"numpy FP64 oracle, fwd+inv of {n} images of the 512x512, 49-filter batch (cycling through "
+                  f"the 16), {dt:.1f} s; numpy.fft runs single-threaded",
     }
 
 
@@ -111,7 +124,13 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--cpu-images", type=int, default=2, help="images in the oracle baseline sample (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle baseline sample length (0 = skip)")
+    ap.add_argument("--path", default="separate", choices=("pipeline", "separate", "persistent"),
+                    help="execution path of the transform calls")
+    ap.add_argument("--chunk", type=int, default=0, help="pipeline: images per chunk (0 = library default)")
+    ap.add_argument("--fpb", type=int, default=0, help="pipeline: filters per column block (0 = library default)")
+    ap.add_argument("--chunk-images", type=int, default=0,
+                    help="images per chunk of the K-expanded intermediate (0 = whole batch)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); run with --gpus 1",
@@ -130,7 +149,12 @@ def main() -> int:
     dev = torch.device("cuda:0")
     log("bench: building system 512x512 J=4")
     t0 = time.perf_counter()
-    shs = ShearletSystem.build(N, M, J)
+    cap = 0
+    if args.chunk_images > 0:
+        pb = N * (M // 2) * 8
+        cap = B * pb + args.chunk_images * 49 * pb
+    shs = ShearletSystem.build(N, M, J, max_workspace_bytes=cap)
+    shs.set_path(args.path, args.chunk, args.fpb)
     build_s = time.perf_counter() - t0
     K = shs.K
     S, _ = shs.export_spectra()
@@ -164,6 +188,7 @@ def main() -> int:
     ms_total = ev0.elapsed_time(ev1)
     rec = shs.profile_read()
     shs.profile(False)
+    shs.check()
     ms_step = ms_total / args.steps
     log(f"bench: {args.steps} timed steps, {ms_step:.3f} ms/step")
 
@@ -180,12 +205,12 @@ def main() -> int:
         if n == 0:
             continue
         avg = tot / n
-        ab = kernel_algorithmic_bytes(kind, K, real_filters)
-        kernels[kind] = {"launches": n, "avg_ms": avg, "share": tot / ms_total,
+        ab = kernel_algorithmic_bytes(kind, K, real_filters) * args.steps / n  # per launch
+        kernels[kind] = {"launches": n, "avg_ms": avg, "share": tot / ms_total, "algorithmic_bytes_per_launch": ab,
                          "algorithmic_GBs": ab / (avg / 1e3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     dk = kernels[dom]
-    ab = kernel_algorithmic_bytes(dom, K, real_filters)
+    ab = dk["algorithmic_bytes_per_launch"]
     achieved = ab / (dk["avg_ms"] / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(dom, 1.0),
@@ -214,8 +239,15 @@ def main() -> int:
         "reconstruction_rel_err": err,
         "system_build_s": build_s,
     }
-    if args.cpu_images > 0:
-        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_images)
+    out["config"]["path"] = args.path
+    if args.chunk:
+        out["config"]["pipeline_chunk_images"] = args.chunk
+    if args.fpb:
+        out["config"]["pipeline_filters_per_block"] = args.fpb
+    if args.chunk_images > 0:
+        out["config"]["chunk_images"] = args.chunk_images
+    if args.cpu_seconds > 0:
+        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_seconds, 64)
     shs.close()
     print(json.dumps(out))
     return 0

@@ -130,7 +130,12 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
 #define SHEAR_KERNEL_ROWS_R2C_COEFFS 3 /* inverse/adjoint: row FFT of the coefficient planes */
 #define SHEAR_KERNEL_COLS_INV 4        /* inverse/adjoint: column FFT, x filter, sum over k, IFFT */
 #define SHEAR_KERNEL_ROWS_C2R_IMAGES 5 /* inverse/adjoint: row inverse FFT -> images   */
-#define SHEAR_KERNEL_KINDS 6
+#define SHEAR_KERNEL_FUSED_FWD 6       /* forward, fused path: kinds 1 + 2 in one persistent kernel */
+#define SHEAR_KERNEL_FUSED_INV 7       /* inverse/adjoint, fused path: kinds 3 + 4 in one persistent kernel */
+#define SHEAR_KERNEL_PIPE_FWD 8        /* forward, pipeline path: one chunk step (column + row stages) */
+#define SHEAR_KERNEL_PIPE_INV 9        /* inverse/adjoint, pipeline path: one chunk step */
+#define SHEAR_KERNEL_PIPE_FINISH 10    /* inverse/adjoint, pipeline path: sum of partial spectra + column IFFT */
+#define SHEAR_KERNEL_KINDS 11
 
 /* Per-launch timing (tracing). While enabled, every kernel launch of the
  * system is bracketed by two hipEvents recorded on the caller's stream. */
@@ -140,6 +145,34 @@ int shear_profile_enable(shear_system* s, int on);
  * and their summed duration in ms (arrays of SHEAR_KERNEL_KINDS) since the
  * previous read, and clears the record. */
 int shear_profile_read(shear_system* s, int* launches, double* total_ms);
+
+/* Execution paths of the transform calls. All give the same results up to
+ * floating-point rounding; all paths use identical per-element operations and
+ * agree bitwise in the forward direction.
+ *   SHEAR_PATH_SEPARATE (default): one launch per stage over the whole batch
+ *     (or workspace-limited chunks) through a batch-sized intermediate; all sizes.
+ *   SHEAR_PATH_PIPELINE (rows, cols in {128, 256, 512, 1024}):
+ *     the batch is processed in chunks of images; each launch runs the
+ *     column stage of one chunk together with the coefficient row stage of
+ *     the neighbouring chunk, exchanging planes through two buffers of
+ *     chunk_images * K planes that stay in the on-package cache.
+ *   SHEAR_PATH_PERSISTENT: one cooperative persistent kernel per direction
+ *     with fine-grained agent-scope synchronisation (slow on this hardware;
+ *     kept for study). */
+#define SHEAR_PATH_PIPELINE 0
+#define SHEAR_PATH_SEPARATE 1
+#define SHEAR_PATH_PERSISTENT 2
+
+/* Selects the path of later transform calls. chunk_images (> 0) sets the
+ * pipeline chunk, filters_per_block (> 0) the filters one pipeline column
+ * block processes; 0 keeps the current value. SHEAR_E_SIZE if the path does
+ * not support the system's size. */
+int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_block);
+
+/* Waits for hip_stream, then reports SHEAR_E_HIP if the last fused launch of
+ * the system gave up on a dependency wait (its output is then invalid). The
+ * fused kernels bound every wait, so they always terminate. */
+int shear_check(shear_system* s, void* hip_stream);
 
 /* Frees a system. The caller must have synchronised every stream that used it. */
 void shear_destroy_system(shear_system* s);

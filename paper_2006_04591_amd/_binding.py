@@ -37,6 +37,8 @@ EXPORTED = (
     "shear_adjoint",
     "shear_profile_enable",
     "shear_profile_read",
+    "shear_set_path",
+    "shear_check",
     "shear_destroy_system",
     "shear_strerror",
     "shear_last_error",
@@ -94,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in EXPORTED:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
+    lib.shear_set_path.argtypes = [P, I, I, I]
+    lib.shear_check.argtypes = [P, P]
     lib.shear_profile_enable.argtypes = [P, I]
     lib.shear_profile_read.argtypes = [P, pI, pD]
     lib.shear_destroy_system.argtypes = [P]
@@ -265,8 +269,21 @@ class ShearletSystem:
         """shear_adjoint: coefficients (B, K, rows, cols) -> images (B, rows, cols)."""
         return self._inv(self._lib.shear_adjoint, "shear_adjoint", coeffs, out, stream)
 
+    # ------------------------------------------------------------ execution path
+    PATHS = {"pipeline": 0, "separate": 1, "persistent": 2}
+
+    def set_path(self, path: str, chunk_images: int = 0, filters_per_block: int = 0) -> None:
+        """Execution path: "pipeline" (default where supported), "separate" or "persistent" (shear_set_path)."""
+        _check(self._lib.shear_set_path(self._h, self.PATHS[path], int(chunk_images), int(filters_per_block)),
+               "shear_set_path")
+
+    def check(self, stream=None) -> None:
+        """Waits for the stream and raises if the last fused launch gave up on a dependency (shear_check)."""
+        _check(self._lib.shear_check(self._h, _stream_ptr(stream)), "shear_check")
+
     # ------------------------------------------------------------ tracing
-    KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images")
+    KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images",
+                    "fused_fwd", "fused_inv", "pipe_fwd", "pipe_inv", "pipe_finish")
 
     def profile(self, on: bool = True) -> None:
         """Brackets every launch with hipEvents on the caller's stream (shear_profile_enable)."""
@@ -274,8 +291,8 @@ class ShearletSystem:
 
     def profile_read(self) -> dict:
         """{kind: (launches, total_ms)} since the last read (shear_profile_read); waits for the events."""
-        n = (ctypes.c_int * 6)()
-        ms = (ctypes.c_double * 6)()
+        n = (ctypes.c_int * len(self.KERNEL_KINDS))()
+        ms = (ctypes.c_double * len(self.KERNEL_KINDS))()
         _check(self._lib.shear_profile_read(self._h, n, ms), "shear_profile_read")
         return {k: (n[i], ms[i]) for i, k in enumerate(self.KERNEL_KINDS)}
 

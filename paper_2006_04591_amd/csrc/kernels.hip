@@ -14,6 +14,8 @@
 // holds P points: on input x[t + T q], on output X[t + T q], q < P.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace shear {
 namespace {
 
@@ -30,6 +32,17 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 template <bool INV>
 __device__ __forceinline__ float2 mul_mi(float2 a) {
     return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+
+// Streaming global accesses (each byte touched once per launch): non-temporal hints.
+typedef float v2f __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 ld_stream(const float2* p) {
+    const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_stream(float2* p, float2 a) {
+    const v2f v = {a.x, a.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<v2f*>(p));
 }
 
 // ---------------------------------------------------------------- butterflies
@@ -133,12 +146,38 @@ __device__ __forceinline__ void dft(float2* v) {
     }
 }
 
+// ---------------------------------------------------------------- wave-level sync
+// Every FFT group (T = L/P <= 64 threads, aligned) lives inside one wavefront,
+// and its LDS scratch is private to the group. LDS operations of a wavefront
+// execute in issue order, so ordering the group's LDS writes before its reads
+// needs only a compiler-level fence, not a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------- Stockham FFT
 // One pass with radix R = min(P, L/NS) over the L points of an FFT group.
 // FIRST: inputs come from registers; LAST: outputs go to registers. Otherwise
 // the pass reads the group's LDS scratch s (L float2), synchronises, and
-// writes back. Every pass that reads LDS ends its read phase with a barrier,
-// so a following pass (or a following FFT) may write s immediately.
+// writes back. Every pass that reads LDS ends its read phase with a sync, so a
+// following pass (or a following FFT) may write s immediately.
+// LDS layout of one exchange between passes. A pass with stride NS and radix R
+// writes runs of NS consecutive addresses spaced NS*R apart; inserting NS
+// padding slots every NS*R slots puts consecutive runs on distinct banks.
+// The next pass reads consecutive addresses, which the padding keeps
+// consecutive within each 16-aligned lane group. Runs of 16 or more need no
+// padding. Footprint: L + L/R slots.
+template <int NS, int R>
+__device__ __forceinline__ int xmap(int a) {
+    if constexpr (NS >= 16) {
+        return a;
+    } else {
+        return a + NS * (a / (NS * R));
+    }
+}
+
 template <int L, int P, bool INV, int NS, bool FIRST>
 struct FFTPass {
     static __device__ __forceinline__ void run(float2 (&v)[P], float2* s, int t, const float2* __restrict__ tw) {
@@ -151,12 +190,13 @@ struct FFTPass {
 #pragma unroll
             for (int q = 0; q < P; ++q) u[q] = v[q];
         } else {
-            __syncthreads();
+            static_assert(T <= 64, "an FFT group must fit in one wavefront");
+            wave_sync();
 #pragma unroll
             for (int i = 0; i < BPT; ++i)
 #pragma unroll
-                for (int r = 0; r < R; ++r) u[i + BPT * r] = s[(t + T * i) + r * (L / R)];
-            __syncthreads();
+                for (int r = 0; r < R; ++r) u[i + BPT * r] = s[xmap<NS / P, P>((t + T * i) + r * (L / R))];
+            wave_sync();
         }
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {
@@ -180,7 +220,7 @@ struct FFTPass {
             } else {
                 const int idxD = (j / NS) * NS * R + (j & (NS - 1));
 #pragma unroll
-                for (int r = 0; r < R; ++r) s[idxD + r * NS] = w[r];
+                for (int r = 0; r < R; ++r) s[xmap<NS, R>(idxD + r * NS)] = w[r];
             }
         }
         if constexpr (!LAST) FFTPass<L, P, INV, NS * R, false>::run(v, s, t, tw);
@@ -192,41 +232,55 @@ __device__ __forceinline__ void fft(float2 (&v)[P], float2* s, int t, const floa
     FFTPass<L, P, INV, 1, true>::run(v, s, t, tw);
 }
 
-// points per thread for an FFT of length L
+// points per thread for an FFT of length L (standalone kernels)
 template <int L>
 struct Pts {
     static constexpr int value = (L >= 1024) ? 16 : (L == 256 ? 16 : 8);
 };
 
-constexpr int RB = 16;  // rows per block in the row passes
+constexpr int RB = 16;  // rows per block in the standalone row passes
 
-// ---------------------------------------------------------------- row passes
+template <bool REAL>
+__device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, float2 a) {
+    if constexpr (REAL) {
+        return cscale(a, reinterpret_cast<const float*>(f)[i]);
+    } else {
+        return cmul(a, reinterpret_cast<const float2*>(f)[i]);
+    }
+}
 
-// TAG only separates launch roles into distinct symbols (0: images, 1: coefficient planes)
-template <int M, int TAG>
-__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(const float* __restrict__ in,
-                                                                             float2* __restrict__ out, int N,
-                                                                             const float2* __restrict__ twL,
-                                                                             const float2* __restrict__ twM) {
-    constexpr int L = M / 2, P = Pts<L>::value, T = L / P, PITCH = L + 1;
-    extern __shared__ float2 lds[];
+// ---------------------------------------------------------------- row tiles
+// A tile is ROWS consecutive rows of one plane, handled by ROWS * (L/P) threads
+// (thread t of row r is threadIdx.x = t + (L/P) r). lds holds ROWS * (L + 1) float2.
+// The caller separates consecutive tiles that reuse lds with a barrier.
+
+// real rows -> packed spectra, column-major plane out[k * N + row]
+// per-row LDS pitch of the row tiles: FFT scratch footprint plus one slot, so
+// that column-wise accesses of consecutive rows fall on different banks
+template <int L, int P>
+struct RowPitch {
+    static constexpr int value = L + L / P + 1;
+};
+
+template <int M, int P, int ROWS>
+__device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane, float2* __restrict__ out_plane, int N,
+                                             int row0, float2* lds, const float2* __restrict__ twL,
+                                             const float2* __restrict__ twM) {
+    constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
     const int tid = threadIdx.x;
-    const int nrb = N / RB;
-    const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * RB;
     const int t = tid % T, r = tid / T;
     float2* s = lds + r * PITCH;
-    const float2* src = reinterpret_cast<const float2*>(in + ((size_t)plane * N + row0 + r) * M);
+    const float2* src = reinterpret_cast<const float2*>(in_plane + (size_t)(row0 + r) * M);
     float2 v[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) v[q] = src[t + T * q];
+    for (int q = 0; q < P; ++q) v[q] = ld_stream(src + t + T * q);
     fft<L, P, false>(v, s, t, twL);
 #pragma unroll
     for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
     __syncthreads();
-    const int r2 = tid % RB, kk = tid / RB;
+    const int r2 = tid % ROWS, kk = tid / ROWS;
     const float2* s2 = lds + r2 * PITCH;
-    float2* dst = out + (size_t)plane * L * N + row0 + r2;
+    float2* dst = out_plane + row0 + r2;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int k = kk + T * i;
@@ -241,30 +295,25 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(con
             const float2 O = make_float2(D.y, -D.x);  // (Z - conj Zm) / (2i)
             X = cadd(E, cmul(twM[k], O));
         }
-        dst[(size_t)k * N] = X;
+        st_stream(dst + (size_t)k * N, X);
     }
 }
 
-template <int M, int TAG>
-__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(const float2* __restrict__ in,
-                                                                             float* __restrict__ out, int N,
-                                                                             const float2* __restrict__ twL,
-                                                                             const float2* __restrict__ twM,
-                                                                             float scale) {
-    constexpr int L = M / 2, P = Pts<L>::value, T = L / P, PITCH = L + 1;
-    extern __shared__ float2 lds[];
+// packed column-major spectra -> real rows, out = scale * unnormalised inverse
+template <int M, int P, int ROWS>
+__device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane, float* __restrict__ out_plane, int N,
+                                             int row0, float2* lds, const float2* __restrict__ twL,
+                                             const float2* __restrict__ twM, float scale) {
+    constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
     const int tid = threadIdx.x;
-    const int nrb = N / RB;
-    const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * RB;
     {
-        const int r2 = tid % RB, kk = tid / RB;
+        const int r2 = tid % ROWS, kk = tid / ROWS;
         float2* s2 = lds + r2 * PITCH;
-        const float2* src = in + (size_t)plane * L * N + row0 + r2;
+        const float2* src = in_plane + row0 + r2;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int k = kk + T * i;
-            s2[k] = src[(size_t)k * N];
+            s2[k] = ld_stream(src + (size_t)k * N);
         }
     }
     __syncthreads();
@@ -287,47 +336,32 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(con
     }
     __syncthreads();
     fft<L, P, true>(v, s, t, twL);
-    float2* dst = reinterpret_cast<float2*>(out + ((size_t)plane * N + row0 + r) * M);
+    float2* dst = reinterpret_cast<float2*>(out_plane + (size_t)(row0 + r) * M);
 #pragma unroll
-    for (int q = 0; q < P; ++q) dst[t + T * q] = cscale(v[q], scale);
+    for (int q = 0; q < P; ++q) st_stream(dst + t + T * q, cscale(v[q], scale));
 }
 
-// ---------------------------------------------------------------- column passes
-
-template <int N, int PW>
-struct ColCfg {
-    static constexpr int P = Pts<N>::value;
-    static constexpr int T = N / P;
-    static constexpr int THREADS = PW * T;
-    static constexpr size_t LDS = (size_t)(PW + 1) * N * sizeof(float2);
+// ---------------------------------------------------------------- column panels
+// A panel is PW consecutive columns [col0, col0 + PW) of an N x L packed plane
+// stored column-major (element (row, col) at col * N + row), handled by
+// PW * (N/P) threads: thread t of panel column c is threadIdx.x = t + (N/P) c.
+// lds holds PW FFT scratches of ColScratch<N, P> float2 plus the N-float2
+// mirror buffer used by packed column 0.
+template <int N, int P>
+struct ColScratch {
+    static constexpr int value = N + N / P;
 };
 
-template <bool REAL>
-__device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, float2 a) {
-    if constexpr (REAL) {
-        return cscale(a, reinterpret_cast<const float*>(f)[i]);
-    } else {
-        return cmul(a, reinterpret_cast<const float2*>(f)[i]);
-    }
-}
-
-template <int N, int PW, bool REAL>
-__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const float2* __restrict__ A,
-                                                                    float2* __restrict__ Tout,
-                                                                    const void* __restrict__ filt, int L, int K,
-                                                                    int npan, const float2* __restrict__ twN,
-                                                                    float scale) {
-    using C = ColCfg<N, PW>;
-    constexpr int P = C::P, T = C::T;
-    extern __shared__ float2 lds[];
-    const int tid = threadIdx.x;
-    const int t = tid % T, c = tid / T;
-    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
-    const int col = pan * PW + c;
-    float2* s = lds + c * N;
-    float2* smir = lds + PW * N;
-    const float2* a = A + ((size_t)b * L + col) * N;
-    float2 xh[P];
+// X = scale * colFFT(a panel); column 0's spectrum is also left in the mirror buffer.
+template <int N, int P, int PW>
+__device__ __forceinline__ void col_fwd_setup(const float2* __restrict__ a_img, int col0, float2 (&xh)[P], float2* lds,
+                                              float scale, const float2* __restrict__ twN) {
+    constexpr int T = N / P;
+    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int col = col0 + c;
+    float2* s = lds + c * ColScratch<N, P>::value;
+    float2* smir = lds + PW * ColScratch<N, P>::value;
+    const float2* a = a_img + (size_t)col * N;
 #pragma unroll
     for (int q = 0; q < P; ++q) xh[q] = cscale(a[t + T * q], scale);
     fft<N, P, false>(xh, s, t, twN);
@@ -336,60 +370,72 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const flo
         for (int q = 0; q < P; ++q) smir[t + T * q] = xh[q];
     }
     __syncthreads();
+}
+
+// out panel = colIFFT(filter_k (.) X); packed column 0 uses alpha X(m) + beta conj X(-m).
+template <int N, int P, int PW, bool REAL>
+__device__ __forceinline__ void col_fwd_emit(const float2 (&xh)[P], const void* __restrict__ filt, int k, int L,
+                                             int col0, float2* __restrict__ out_plane, float2* lds,
+                                             const float2* __restrict__ twN) {
+    constexpr int T = N / P;
+    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int col = col0 + c;
+    float2* s = lds + c * ColScratch<N, P>::value;
+    const float2* smir = lds + PW * ColScratch<N, P>::value;
     const size_t fstride = (size_t)(L + 1) * N;
-    for (int k = 0; k < K; ++k) {
-        const size_t fbase = (size_t)k * fstride + (size_t)col * N;
-        float2 y[P];
+    const size_t fbase = (size_t)k * fstride + (size_t)col * N;
+    float2 y[P];
 #pragma unroll
-        for (int q = 0; q < P; ++q) y[q] = fmul<REAL>(filt, fbase + t + T * q, xh[q]);
-        if (col == 0) {
-            const size_t bbase = (size_t)k * fstride + (size_t)L * N;
+    for (int q = 0; q < P; ++q) y[q] = fmul<REAL>(filt, fbase + t + T * q, xh[q]);
+    if (col == 0) {
+        const size_t bbase = (size_t)k * fstride + (size_t)L * N;
 #pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const int m = t + T * q;
-                y[q] = cadd(y[q], fmul<REAL>(filt, bbase + m, cconj(smir[(N - m) & (N - 1)])));
-            }
+        for (int q = 0; q < P; ++q) {
+            const int m = t + T * q;
+            y[q] = cadd(y[q], fmul<REAL>(filt, bbase + m, cconj(smir[(N - m) & (N - 1)])));
         }
-        fft<N, P, true>(y, s, t, twN);
-        float2* o = Tout + (((size_t)b * K + k) * L + col) * N;
+    }
+    fft<N, P, true>(y, s, t, twN);
+    float2* o = out_plane + (size_t)col * N;
 #pragma unroll
-        for (int q = 0; q < P; ++q) o[t + T * q] = y[q];
+    for (int q = 0; q < P; ++q) st_stream(o + t + T * q, y[q]);
+}
+
+// acc += filter_k (.) colFFT(u panel); packed column 0 also accumulates g for the mirrored term.
+template <int N, int P, int PW, bool REAL>
+__device__ __forceinline__ void col_inv_accum(const float2* __restrict__ u_plane, const void* __restrict__ filt, int k,
+                                              int L, int col0, float2 (&acc)[P], float2 (&g)[P], float2* lds,
+                                              const float2* __restrict__ twN) {
+    constexpr int T = N / P;
+    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int col = col0 + c;
+    float2* s = lds + c * ColScratch<N, P>::value;
+    const float2* u = u_plane + (size_t)col * N;
+    float2 x[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) x[q] = ld_stream(u + t + T * q);
+    fft<N, P, false>(x, s, t, twN);
+    const size_t fstride = (size_t)(L + 1) * N;
+    const size_t fbase = (size_t)k * fstride + (size_t)col * N;
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = cadd(acc[q], fmul<REAL>(filt, fbase + t + T * q, x[q]));
+    if (col == 0) {
+        const size_t gbase = (size_t)k * fstride + (size_t)L * N;
+#pragma unroll
+        for (int q = 0; q < P; ++q) g[q] = cadd(g[q], fmul<REAL>(filt, gbase + t + T * q, x[q]));
     }
 }
 
-template <int N, int PW, bool REAL>
-__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const float2* __restrict__ U,
-                                                                    float2* __restrict__ V,
-                                                                    const void* __restrict__ filt, int L, int K,
-                                                                    int npan, const float2* __restrict__ twN) {
-    using C = ColCfg<N, PW>;
-    constexpr int P = C::P, T = C::T;
-    extern __shared__ float2 lds[];
-    const int tid = threadIdx.x;
-    const int t = tid % T, c = tid / T;
-    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
-    const int col = pan * PW + c;
-    float2* s = lds + c * N;
-    float2* smir = lds + PW * N;
-    float2 acc[P], g[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) acc[q] = g[q] = make_float2(0.0f, 0.0f);
-    const size_t fstride = (size_t)(L + 1) * N;
-    for (int k = 0; k < K; ++k) {
-        const float2* u = U + (((size_t)b * K + k) * L + col) * N;
-        float2 x[P];
-#pragma unroll
-        for (int q = 0; q < P; ++q) x[q] = u[t + T * q];
-        fft<N, P, false>(x, s, t, twN);
-        const size_t fbase = (size_t)k * fstride + (size_t)col * N;
-#pragma unroll
-        for (int q = 0; q < P; ++q) acc[q] = cadd(acc[q], fmul<REAL>(filt, fbase + t + T * q, x[q]));
-        if (col == 0) {
-            const size_t gbase = (size_t)k * fstride + (size_t)L * N;
-#pragma unroll
-            for (int q = 0; q < P; ++q) g[q] = cadd(g[q], fmul<REAL>(filt, gbase + t + T * q, x[q]));
-        }
-    }
+// v panel = colIFFT(acc + [column 0: conj g(-m)])
+template <int N, int P, int PW>
+__device__ __forceinline__ void col_inv_finish(float2 (&acc)[P], const float2 (&g)[P], int col0, float2* __restrict__ v_img,
+                                               float2* lds, const float2* __restrict__ twN) {
+    constexpr int T = N / P;
+    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int col = col0 + c;
+    float2* s = lds + c * ColScratch<N, P>::value;
+    float2* smir = lds + PW * ColScratch<N, P>::value;
+    __syncthreads();  // the mirror buffer may still be read by a previous user
     if (col == 0) {
 #pragma unroll
         for (int q = 0; q < P; ++q) smir[t + T * q] = g[q];
@@ -403,9 +449,337 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const flo
         }
     }
     fft<N, P, true>(acc, s, t, twN);
-    float2* o = V + ((size_t)b * L + col) * N;
+    float2* o = v_img + (size_t)col * N;
 #pragma unroll
     for (int q = 0; q < P; ++q) o[t + T * q] = acc[q];
+}
+
+// ---------------------------------------------------------------- standalone kernels
+
+// TAG only separates launch roles into distinct symbols (0: images, 1: coefficient planes)
+template <int M, int TAG>
+__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(const float* __restrict__ in,
+                                                                             float2* __restrict__ out, int N,
+                                                                             const float2* __restrict__ twL,
+                                                                             const float2* __restrict__ twM) {
+    constexpr int L = M / 2;
+    extern __shared__ float2 lds[];
+    const int nrb = N / RB;
+    const int plane = blockIdx.x / nrb;
+    const int row0 = (blockIdx.x % nrb) * RB;
+    row_r2c_tile<M, Pts<L>::value, RB>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM);
+}
+
+template <int M, int TAG>
+__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(const float2* __restrict__ in,
+                                                                             float* __restrict__ out, int N,
+                                                                             const float2* __restrict__ twL,
+                                                                             const float2* __restrict__ twM,
+                                                                             float scale) {
+    constexpr int L = M / 2;
+    extern __shared__ float2 lds[];
+    const int nrb = N / RB;
+    const int plane = blockIdx.x / nrb;
+    const int row0 = (blockIdx.x % nrb) * RB;
+    row_c2r_tile<M, Pts<L>::value, RB>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL, twM,
+                                       scale);
+}
+
+template <int N, int PW>
+struct ColCfg {
+    static constexpr int P = Pts<N>::value;
+    static constexpr int T = N / P;
+    static constexpr int THREADS = PW * T;
+    static constexpr size_t LDS = ((size_t)PW * ColScratch<N, P>::value + N) * sizeof(float2);
+};
+
+template <int N, int PW, bool REAL>
+__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const float2* __restrict__ A,
+                                                                    float2* __restrict__ Tout,
+                                                                    const void* __restrict__ filt, int L, int K,
+                                                                    int npan, const float2* __restrict__ twN,
+                                                                    float scale) {
+    constexpr int P = ColCfg<N, PW>::P;
+    extern __shared__ float2 lds[];
+    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
+    float2 xh[P];
+    col_fwd_setup<N, P, PW>(A + (size_t)b * L * N, pan * PW, xh, lds, scale, twN);
+    for (int k = 0; k < K; ++k)
+        col_fwd_emit<N, P, PW, REAL>(xh, filt, k, L, pan * PW, Tout + ((size_t)b * K + k) * L * N, lds, twN);
+}
+
+template <int N, int PW, bool REAL>
+__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const float2* __restrict__ U,
+                                                                    float2* __restrict__ V,
+                                                                    const void* __restrict__ filt, int L, int K,
+                                                                    int npan, const float2* __restrict__ twN) {
+    constexpr int P = ColCfg<N, PW>::P;
+    extern __shared__ float2 lds[];
+    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
+    float2 acc[P], g[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = g[q] = make_float2(0.0f, 0.0f);
+    for (int k = 0; k < K; ++k)
+        col_inv_accum<N, P, PW, REAL>(U + ((size_t)b * K + k) * L * N, filt, k, L, pan * PW, acc, g, lds, twN);
+    col_inv_finish<N, P, PW>(acc, g, pan * PW, V + (size_t)b * L * N, lds, twN);
+}
+
+// ---------------------------------------------------------------- fused persistent kernels
+// One cooperative launch per transform direction fuses the column stage and
+// the coefficient row stage. Work is cut into tasks on an (image, filter)
+// plane: column tasks (one panel of PW columns, looping over all K filters)
+// and row tasks (ROWS rows of one plane). Each plane is exchanged between the
+// two stages through one slot of a small ring (S slots per image in flight),
+// so the exchange stays on chip-side caches instead of making a full round
+// trip through HBM. Tasks live on Q logical queues (queue = block id mod Q);
+// an image's tasks all go to one queue, so with round-robin block placement
+// its exchange slots are produced and consumed within one XCD.
+//
+// Ordering: a producer drains its wave's memory operations, the block
+// barriers, and one thread publishes with an agent-scope release increment;
+// a consumer's thread spins on a relaxed agent-scope load, then issues an
+// agent-scope acquire fence before the block barrier. Queue order lists every
+// task after the tasks it waits on, except the long column tasks, which are
+// dequeued first in their group; the host keeps their number below the blocks
+// per queue, so row tasks always find blocks. Every spin is bounded: on
+// timeout it raises an abort flag that makes all other waits give up, so the
+// kernel always drains; the host reports the flag through shear_check.
+
+constexpr int SPIN_LIMIT = 1 << 18;
+
+__device__ __forceinline__ bool spin_geq(unsigned* ctr, unsigned target, unsigned* abort_flag) {
+    for (int it = 0; it < SPIN_LIMIT; ++it) {
+        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            return true;
+        }
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+}
+
+// Block-wide wait until *ctr >= target. All threads call it; returns false on abort.
+__device__ __forceinline__ bool block_wait(unsigned* ctr, unsigned target, unsigned* abort_flag, int* sh_ok) {
+    if (threadIdx.x == 0) *sh_ok = spin_geq(ctr, target, abort_flag) ? 1 : 0;
+    __syncthreads();
+    return *sh_ok != 0;
+}
+
+// Block-wide publish: every wave's loads and stores complete, then one agent-scope release increment.
+__device__ __forceinline__ void block_signal(unsigned* ctr) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int N, int M, int PC, int PW, int PR>
+struct FusedCfg {
+    static constexpr int L = M / 2;
+    static constexpr int TC = N / PC;
+    static constexpr int THREADS = PW * TC;
+    static constexpr int TR = L / PR;
+    static constexpr int ROWS = THREADS / TR;
+    static_assert(ROWS * TR == THREADS && ROWS >= 1, "row tile must use the whole block");
+    static constexpr size_t LDS_COL = ((size_t)PW * ColScratch<N, PC>::value + N) * sizeof(float2);
+    static constexpr size_t LDS_ROW = (size_t)ROWS * RowPitch<L, PR>::value * sizeof(float2);
+    static constexpr size_t LDS = LDS_COL > LDS_ROW ? LDS_COL : LDS_ROW;
+};
+
+template <int N, int M, int PC, int PW, int PR, bool REAL, bool FWD>
+__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS), 4) void k_fused(FusedGeom g, FusedBufs bf) {
+    using C = FusedCfg<N, M, PC, PW, PR>;
+    constexpr int L = C::L, ROWS = C::ROWS;
+    extern __shared__ float2 lds[];
+    __shared__ int sh_task, sh_ok;
+    const int q = blockIdx.x % g.Q;
+    const int nq = (q < g.B) ? (g.B - q + g.Q - 1) / g.Q : 0;
+    const int per_img = g.npan + g.K * g.nrb;
+    const int total = nq * per_img;
+    const int FG = g.GI * per_img;
+    const int nslots = g.Q * g.ng * g.GI * g.S;
+    unsigned* done = bf.ctr;  // slot s: [2s] column-side count, [2s+1] row-side count
+    unsigned* heads = bf.ctr + 2 * nslots;
+    unsigned* abort_flag = heads + g.Q;
+    const size_t plane = (size_t)L * N;
+    for (;;) {
+        __syncthreads();  // the previous task's LDS and shared reads are finished
+        if (threadIdx.x == 0) sh_task = (int)atomicAdd(&heads[q], 1u);
+        __syncthreads();
+        const int task = sh_task;
+        if (task >= total) return;
+        const int grp = task / FG, rem = task % FG;
+        const int gi = min(g.GI, nq - grp * g.GI);
+        const int sbase0 = (q * g.ng + grp) * g.GI * g.S;
+        if (rem < gi * g.npan) {
+            // ---------------- column task: panel p of image i, all K planes
+            const int i = rem / g.npan, p = rem % g.npan;
+            const int b = q + g.Q * (grp * g.GI + i);
+            const int sbase = sbase0 + i * g.S;
+            if constexpr (FWD) {
+                float2 xh[PC];
+                col_fwd_setup<N, PC, PW>(bf.A + (size_t)b * plane, p * PW, xh, lds, bf.scale, bf.twN);
+                for (int k = 0; k < g.K; ++k) {
+                    const int sid = sbase + k % g.S;
+                    const unsigned u = (unsigned)(k / g.S);
+                    // the slot's previous plane must have been read by all its row tiles
+                    if (u > 0 && !block_wait(&done[2 * sid + 1], u * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
+                    col_fwd_emit<N, PC, PW, REAL>(xh, bf.filt, k, L, p * PW, bf.slots + (size_t)sid * plane, lds,
+                                                  bf.twN);
+                    block_signal(&done[2 * sid]);
+                }
+            } else {
+                float2 acc[PC], gg[PC];
+#pragma unroll
+                for (int qq = 0; qq < PC; ++qq) acc[qq] = gg[qq] = make_float2(0.0f, 0.0f);
+                for (int k = 0; k < g.K; ++k) {
+                    const int sid = sbase + k % g.S;
+                    const unsigned u = (unsigned)(k / g.S);
+                    // the plane's row tiles must all be written
+                    if (!block_wait(&done[2 * sid + 1], (u + 1) * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
+                    col_inv_accum<N, PC, PW, REAL>(bf.slots + (size_t)sid * plane, bf.filt, k, L, p * PW, acc, gg, lds,
+                                                   bf.twN);
+                    block_signal(&done[2 * sid]);
+                }
+                col_inv_finish<N, PC, PW>(acc, gg, p * PW, bf.V + (size_t)b * plane, lds, bf.twN);
+            }
+        } else {
+            // ---------------- row task: tile r of plane (i, k)
+            const int r2 = rem - gi * g.npan;
+            const int k = r2 / (gi * g.nrb);
+            const int i = (r2 / g.nrb) % gi;
+            const int r = r2 % g.nrb;
+            const int b = q + g.Q * (grp * g.GI + i);
+            const int sid = sbase0 + i * g.S + k % g.S;
+            const unsigned u = (unsigned)(k / g.S);
+            const size_t img = (size_t)N * M;
+            if constexpr (FWD) {
+                // all column panels of this plane must be written
+                if (!block_wait(&done[2 * sid], (u + 1) * (unsigned)g.npan, abort_flag, &sh_ok)) return;
+                row_c2r_tile<M, PR, ROWS>(bf.slots + (size_t)sid * plane, bf.cout + ((size_t)b * g.K + k) * img, N,
+                                          r * ROWS, lds, bf.twL, bf.twM, 1.0f);
+            } else {
+                // the slot's previous plane must have been read by all column panels
+                if (u > 0 && !block_wait(&done[2 * sid], u * (unsigned)g.npan, abort_flag, &sh_ok)) return;
+                row_r2c_tile<M, PR, ROWS>(bf.cin + ((size_t)b * g.K + k) * img, bf.slots + (size_t)sid * plane, N,
+                                          r * ROWS, lds, bf.twL, bf.twM);
+            }
+            block_signal(&done[2 * sid + 1]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- skewed pipeline kernels
+// The batch is cut into chunks of images. Launch i of the forward transform
+// runs the column stage of chunk i+1 and the coefficient row stage of chunk i
+// as one grid (column blocks first), exchanging planes through two ping-pong
+// buffers sized to stay in the on-package cache; kernel boundaries order the
+// stages, so no block waits on another. The inverse runs the coefficient row
+// stage of chunk i+1 with the column stage of chunk i, whose blocks each sum
+// one group of filters into a partial spectrum; one more launch adds the
+// partials in a fixed order and applies the column IFFT.
+
+template <int N, int M, int PC, int PW, int PR, bool REAL>
+__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_fwd(SkewArgs a) {
+    using C = FusedCfg<N, M, PC, PW, PR>;
+    constexpr int L = C::L, ROWS = C::ROWS;
+    extern __shared__ float2 lds[];
+    const size_t plane = (size_t)L * N;
+    const int ncol = a.col_nb * a.npan * a.kg;
+    int task = blockIdx.x;
+    if (task < ncol) {
+        const int g = task % a.kg;
+        const int p = (task / a.kg) % a.npan;
+        const int i = task / (a.kg * a.npan);
+        const int b = a.col_b0 + i;
+        float2 xh[PC];
+        col_fwd_setup<N, PC, PW>(a.A + (size_t)b * plane, p * PW, xh, lds, a.scale, a.twN);
+        const int k1 = min(a.K, (g + 1) * a.kper);
+        for (int k = g * a.kper; k < k1; ++k)
+            col_fwd_emit<N, PC, PW, REAL>(xh, a.filt, k, L, p * PW, a.bufC + ((size_t)i * a.K + k) * plane, lds, a.twN);
+        return;
+    }
+    task -= ncol;
+    const int r = task % a.nrb;
+    const int k = (task / a.nrb) % a.K;
+    const int i = task / (a.nrb * a.K);
+    const int b = a.row_b0 + i;
+    row_c2r_tile<M, PR, ROWS>(a.bufR + ((size_t)i * a.K + k) * plane, a.cout + ((size_t)b * a.K + k) * N * M, N,
+                              r * ROWS, lds, a.twL, a.twM, 1.0f);
+}
+
+template <int N, int M, int PC, int PW, int PR, bool REAL>
+__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_inv(SkewArgs a) {
+    using C = FusedCfg<N, M, PC, PW, PR>;
+    constexpr int L = C::L, ROWS = C::ROWS, TC = C::TC;
+    extern __shared__ float2 lds[];
+    const size_t plane = (size_t)L * N;
+    const int ncol = a.col_nb * a.npan * a.kg;
+    int task = blockIdx.x;
+    if (task < ncol) {
+        const int g = task % a.kg;
+        const int p = (task / a.kg) % a.npan;
+        const int i = task / (a.kg * a.npan);
+        const int b = a.col_b0 + i;
+        float2 acc[PC], gg[PC];
+#pragma unroll
+        for (int q = 0; q < PC; ++q) acc[q] = gg[q] = make_float2(0.0f, 0.0f);
+        const int k1 = min(a.K, (g + 1) * a.kper);
+        for (int k = g * a.kper; k < k1; ++k)
+            col_inv_accum<N, PC, PW, REAL>(a.bufC + ((size_t)i * a.K + k) * plane, a.filt, k, L, p * PW, acc, gg, lds,
+                                           a.twN);
+        // partial spectrum of filter group g (and, for packed column 0, its mirrored-term partial)
+        const int t = threadIdx.x % TC, c = threadIdx.x / TC;
+        const int col = p * PW + c;
+        float2* o = a.part + ((size_t)b * a.kg + g) * plane + (size_t)col * N;
+#pragma unroll
+        for (int q = 0; q < PC; ++q) o[t + TC * q] = acc[q];
+        if (col == 0) {
+            float2* og = a.part0 + ((size_t)b * a.kg + g) * N;
+#pragma unroll
+            for (int q = 0; q < PC; ++q) og[t + TC * q] = gg[q];
+        }
+        return;
+    }
+    task -= ncol;
+    const int r = task % a.nrb;
+    const int k = (task / a.nrb) % a.K;
+    const int i = task / (a.nrb * a.K);
+    const int b = a.row_b0 + i;
+    row_r2c_tile<M, PR, ROWS>(a.cin + ((size_t)b * a.K + k) * N * M, a.bufR + ((size_t)i * a.K + k) * plane, N,
+                              r * ROWS, lds, a.twL, a.twM);
+}
+
+// V[b] panel p = colIFFT( sum_g partial_g  [+ conj of the mirrored column-0 partials] ), g in order
+template <int N, int M, int PC, int PW, int PR>
+__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_finish(SkewArgs a) {
+    using C = FusedCfg<N, M, PC, PW, PR>;
+    constexpr int L = C::L, TC = C::TC;
+    extern __shared__ float2 lds[];
+    const size_t plane = (size_t)L * N;
+    const int p = blockIdx.x % a.npan, b = blockIdx.x / a.npan;
+    const int t = threadIdx.x % TC, c = threadIdx.x / TC;
+    const int col = p * PW + c;
+    float2 acc[PC], gg[PC];
+#pragma unroll
+    for (int q = 0; q < PC; ++q) acc[q] = gg[q] = make_float2(0.0f, 0.0f);
+    for (int g = 0; g < a.kg; ++g) {
+        const float2* src = a.part + ((size_t)b * a.kg + g) * plane + (size_t)col * N;
+#pragma unroll
+        for (int q = 0; q < PC; ++q) acc[q] = cadd(acc[q], src[t + TC * q]);
+        if (col == 0) {
+            const float2* sg = a.part0 + ((size_t)b * a.kg + g) * N;
+#pragma unroll
+            for (int q = 0; q < PC; ++q) gg[q] = cadd(gg[q], sg[t + TC * q]);
+        }
+    }
+    col_inv_finish<N, PC, PW>(acc, gg, p * PW, a.V + (size_t)b * plane, lds, a.twN);
+}
+
+__global__ void k_zero_u32(unsigned* p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -419,7 +793,7 @@ hipError_t set_lds(F* fn, size_t bytes) {
 template <int M, int TAG>
 hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)RB * (L + 1) * sizeof(float2);
+    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
     hipError_t e = set_lds(k_rows_r2c<M, TAG>, lds);
     if (e != hipSuccess) return e;
     const size_t blocks = (size_t)planes * (d.N / RB);
@@ -430,7 +804,7 @@ hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes
 template <int M, int TAG>
 hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)RB * (L + 1) * sizeof(float2);
+    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
     hipError_t e = set_lds(k_rows_c2r<M, TAG>, lds);
     if (e != hipSuccess) return e;
     const size_t blocks = (size_t)planes * (d.N / RB);
@@ -551,6 +925,165 @@ hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nim
 
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, hipStream_t st) {
     SHEAR_COLS_SWITCH(cols_inv_t, d, U, V, nimg, filt, st)
+}
+
+// ---------------------------------------------------------------- fused dispatch
+namespace {
+
+// Tile configuration of the fused kernels: 512 threads per block, and the same
+// FFT decompositions as the standalone kernels, so both paths round identically.
+template <int N, int M>
+struct FusedPick {
+    static constexpr int PC = Pts<N>::value;
+    static constexpr int PW = 512 / (N / PC);
+    static constexpr int PR = Pts<M / 2>::value;
+    using C = FusedCfg<N, M, PC, PW, PR>;
+};
+
+template <int N, int M, bool REAL, bool FWD>
+const void* fused_fn() {
+    using F = FusedPick<N, M>;
+    return reinterpret_cast<const void*>(&k_fused<N, M, F::PC, F::PW, F::PR, REAL, FWD>);
+}
+
+template <int N, int M>
+hipError_t fused_info_t(const DevPlan& d, bool fwd, FusedInfo& fi) {
+    using F = FusedPick<N, M>;
+    using C = typename F::C;
+    fi.threads = C::THREADS;
+    fi.lds = C::LDS;
+    fi.npan = d.L / F::PW;
+    fi.nrb = d.N / C::ROWS;
+    fi.fn = d.real ? (fwd ? fused_fn<N, M, true, true>() : fused_fn<N, M, true, false>())
+                   : (fwd ? fused_fn<N, M, false, true>() : fused_fn<N, M, false, false>());
+    if (C::LDS > 65536) {
+        hipError_t e = hipFuncSetAttribute(fi.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&fi.blocks_per_cu, fi.fn, C::THREADS, C::LDS);
+}
+
+template <int N>
+hipError_t fused_info_m(const DevPlan& d, bool fwd, FusedInfo& fi) {
+    switch (d.M) {
+        case 128: return fused_info_t<N, 128>(d, fwd, fi);
+        case 256: return fused_info_t<N, 256>(d, fwd, fi);
+        case 512: return fused_info_t<N, 512>(d, fwd, fi);
+        case 1024: return fused_info_t<N, 1024>(d, fwd, fi);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool fused_supported(int N, int M) {
+    auto ok = [](int n) { return n == 128 || n == 256 || n == 512 || n == 1024; };
+    return ok(N) && ok(M);
+}
+
+hipError_t fused_info(const DevPlan& d, bool fwd, FusedInfo& fi) {
+    switch (d.N) {
+        case 128: return fused_info_m<128>(d, fwd, fi);
+        case 256: return fused_info_m<256>(d, fwd, fi);
+        case 512: return fused_info_m<512>(d, fwd, fi);
+        case 1024: return fused_info_m<1024>(d, fwd, fi);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fused(const FusedInfo& fi, const FusedGeom& g, const FusedBufs& bf, int grid, hipStream_t st) {
+    FusedGeom ga = g;
+    FusedBufs ba = bf;
+    void* args[] = {&ga, &ba};
+    return hipLaunchCooperativeKernel(fi.fn, dim3((unsigned)grid), dim3((unsigned)fi.threads), args,
+                                      (unsigned)fi.lds, st);
+}
+
+namespace {
+
+template <int N, int M>
+hipError_t skew_t(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st) {
+    using F = FusedPick<N, M>;
+    using C = typename F::C;
+    const void* fn;
+    if (which == 0)
+        fn = d.real ? reinterpret_cast<const void*>(&k_skew_fwd<N, M, F::PC, F::PW, F::PR, true>)
+                    : reinterpret_cast<const void*>(&k_skew_fwd<N, M, F::PC, F::PW, F::PR, false>);
+    else if (which == 1)
+        fn = d.real ? reinterpret_cast<const void*>(&k_skew_inv<N, M, F::PC, F::PW, F::PR, true>)
+                    : reinterpret_cast<const void*>(&k_skew_inv<N, M, F::PC, F::PW, F::PR, false>);
+    else
+        fn = reinterpret_cast<const void*>(&k_skew_finish<N, M, F::PC, F::PW, F::PR>);
+    if (C::LDS > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+        if (e != hipSuccess) return e;
+    }
+    SkewArgs aa = a;
+    void* args[] = {&aa};
+    return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3((unsigned)C::THREADS), args, C::LDS, st);
+}
+
+template <int N>
+hipError_t skew_m(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st) {
+    switch (d.M) {
+        case 128: return skew_t<N, 128>(d, which, a, blocks, st);
+        case 256: return skew_t<N, 256>(d, which, a, blocks, st);
+        case 512: return skew_t<N, 512>(d, which, a, blocks, st);
+        case 1024: return skew_t<N, 1024>(d, which, a, blocks, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+namespace {
+template <int N, int M>
+SkewTiles tiles_t(const DevPlan& d) {
+    using F = FusedPick<N, M>;
+    SkewTiles t;
+    t.ok = true;
+    t.npan = d.L / F::PW;
+    t.nrb = d.N / F::C::ROWS;
+    return t;
+}
+template <int N>
+SkewTiles tiles_m(const DevPlan& d) {
+    switch (d.M) {
+        case 128: return tiles_t<N, 128>(d);
+        case 256: return tiles_t<N, 256>(d);
+        case 512: return tiles_t<N, 512>(d);
+        case 1024: return tiles_t<N, 1024>(d);
+    }
+    return SkewTiles{};
+}
+}  // namespace
+
+SkewTiles skew_tiles(const DevPlan& d) {
+    switch (d.N) {
+        case 128: return tiles_m<128>(d);
+        case 256: return tiles_m<256>(d);
+        case 512: return tiles_m<512>(d);
+        case 1024: return tiles_m<1024>(d);
+    }
+    return SkewTiles{};
+}
+
+hipError_t launch_skew(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st) {
+    if (blocks <= 0) return hipSuccess;
+    switch (d.N) {
+        case 128: return skew_m<128>(d, which, a, blocks, st);
+        case 256: return skew_m<256>(d, which, a, blocks, st);
+        case 512: return skew_m<512>(d, which, a, blocks, st);
+        case 1024: return skew_m<1024>(d, which, a, blocks, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
+    const int threads = 256;
+    const int blocks = std::max(1, std::min(1024, (n + threads - 1) / threads));
+    hipLaunchKernelGGL(k_zero_u32, dim3(blocks), dim3(threads), 0, st, p, n);
+    return hipGetLastError();
 }
 
 }  // namespace shear
