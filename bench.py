@@ -119,7 +119,76 @@ def cpu_baseline(x_host, min_seconds: float, max_images: int) -> dict:
     }
 
 
+def copy_calibration(mib: int) -> int:
+    """Device-to-device copies of a known size, to calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.arange(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": n * 4, "copies": 3}))
+    return 0
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_csv: str, cal_bytes: int) -> int:
+    """Writes profiles/traffic.json: per-kernel HBM bytes per launch from rocprofv3 counter CSVs
+    (FETCH_SIZE and WRITE_SIZE in KiB per dispatch), each scaled by the factor that makes the
+    same counter read cal_bytes for the calibration copy kernel."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        sums = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Kernel_Name"], r["Dispatch_Id"])
+            sums[key] = sums.get(key, 0.0) + float(r["Counter_Value"]) * 1024.0
+        by = {}
+        for (name, _), v in sums.items():
+            by.setdefault(name, []).append(v)
+        return {k: statistics.mean(v) for k, v in by.items()}
+
+    def copy_factor(path, counter):
+        vals = [v for k, v in per_kernel(path, counter).items() if "shear" not in k and v > cal_bytes / 8]
+        return cal_bytes / statistics.median(vals)
+
+    ff = copy_factor(cal_fetch_csv, "FETCH_SIZE")
+    fw = copy_factor(cal_write_csv, "WRITE_SIZE")
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+    kinds = {"k_rows_r2c<512, 0>": "rows_r2c_images", "k_cols_fwd<": "cols_fwd", "k_rows_c2r<512, 1>": "rows_c2r_coeffs",
+             "k_rows_r2c<512, 1>": "rows_r2c_coeffs", "k_cols_inv<": "cols_inv", "k_rows_c2r<512, 0>": "rows_c2r_images"}
+    out = {}
+    for name in fetch:
+        kind = next((v for k, v in kinds.items() if k in name), None)
+        if kind is None:
+            continue
+        f = fetch[name] * ff
+        w = write.get(name, 0.0) * fw
+        short = name.replace("(anonymous namespace)::", "").split("(")[0]
+        out[kind] = {"kernel": short, "fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w}
+    src = os.path.join(ROOT, "paper_2006_04591_amd", "csrc", "kernels.hip")
+    with open(src, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    rec = {"kernels_hip_sha256": digest, "fetch_scale": ff, "write_scale": fw, "calibration_bytes": cal_bytes,
+           "kernels": out}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+    return 0
+
+
 def main() -> int:
+    if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
+        return copy_calibration(int(sys.argv[2]))
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-summary":
+        a = sys.argv[2:]
+        return traffic_summary(a[0], a[1], a[2], a[3], int(a[4]))
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
