@@ -156,17 +156,21 @@ int shear_profile_read(shear_system* s, int* launches, double* total_ms);
  *     column stage of one chunk together with the coefficient row stage of
  *     the neighbouring chunk, exchanging planes through two buffers of
  *     chunk_images * K planes that stay in the on-package cache.
- *   SHEAR_PATH_PERSISTENT: one cooperative persistent kernel per direction
- *     with fine-grained agent-scope synchronisation (slow on this hardware;
- *     kept for study). */
+ *   SHEAR_PATH_PERSISTENT (rows, cols in {128, 256, 512, 1024}): one
+ *     cooperative persistent kernel per direction fuses the column stage and
+ *     the coefficient row stage; planes pass between them through a ring of
+ *     exchange slots held in the L2 of one XCD (blocks take work only from the
+ *     queue of the XCD they run on), with counter-based waits inside the XCD. */
 #define SHEAR_PATH_PIPELINE 0
 #define SHEAR_PATH_SEPARATE 1
 #define SHEAR_PATH_PERSISTENT 2
 
-/* Selects the path of later transform calls. chunk_images (> 0) sets the
- * pipeline chunk, filters_per_block (> 0) the filters one pipeline column
- * block processes; 0 keeps the current value. SHEAR_E_SIZE if the path does
- * not support the system's size. */
+/* Selects the path of later transform calls. For SHEAR_PATH_PIPELINE,
+ * chunk_images (> 0) sets the chunk and filters_per_block (> 0) the filters
+ * one column block processes. For SHEAR_PATH_PERSISTENT, chunk_images (> 0)
+ * sets the images an XCD transforms at once and filters_per_block (> 0) the
+ * exchange slots per image. 0 keeps the current value. SHEAR_E_SIZE if the
+ * path does not support the system's size. */
 int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_block);
 
 /* Waits for hip_stream, then reports SHEAR_E_HIP if the last fused launch of

@@ -43,18 +43,24 @@ bool size_supported(int n);
 // ---------------------------------------------------------------- fused persistent path
 
 struct FusedGeom {
-    int B, K, L, N;    // batch, filters, packed columns, rows
-    int Q, GI, S, ng;  // queues, images per group, ring slots per image, groups per queue
-    int npan, nrb;     // column panels and row tiles per plane
+    int B, K, L, N;     // batch, filters, packed columns, rows
+    int GI, S, Qmax;    // images per group, ring slots per image, queues (XCDs) the slots are sized for
+    int npan, nrb;      // column panels and row tiles per plane
 };
+
+// Counter words of a fused launch (zeroed before it): census, arrival, abort
+// flag, queue heads, and two per exchange slot.
+constexpr int kFusedMaxXcc = 16;
+inline size_t fused_ctr_words(const FusedGeom& g) { return 2 * kFusedMaxXcc + 2 + 2 * (size_t)g.Qmax * g.GI * g.S; }
+inline size_t fused_abort_word() { return kFusedMaxXcc + 1; }
 
 struct FusedBufs {
     const float2* A;   // forward: unscaled row spectra of the images (B x L x N)
     const float* cin;  // inverse: coefficients (B x K x N x M)
     float* cout;       // forward: coefficients
     float2* V;         // inverse: accumulated spectra (B x L x N)
-    float2* slots;     // Q * ng * GI * S exchange planes of L x N
-    unsigned* ctr;     // [2 * nslots] done counters, [Q] queue heads, [1] abort flag
+    float2* slots;     // Qmax * GI * S exchange planes of L x N
+    unsigned* ctr;     // fused_ctr_words(g) counters
     const void* filt;
     const float2* twN;
     const float2* twL;

@@ -44,6 +44,24 @@ __device__ __forceinline__ void st_stream(float2* p, float2 a) {
     const v2f v = {a.x, a.y};
     __builtin_nontemporal_store(v, reinterpret_cast<v2f*>(p));
 }
+// Accesses of exchange planes: non-temporal when the plane makes a round trip
+// through HBM (NT), ordinary when it is meant to stay in the XCD's L2.
+template <bool NT>
+__device__ __forceinline__ float2 ld_x(const float2* p) {
+    if constexpr (NT) {
+        return ld_stream(p);
+    } else {
+        return *p;
+    }
+}
+template <bool NT>
+__device__ __forceinline__ void st_x(float2* p, float2 a) {
+    if constexpr (NT) {
+        st_stream(p, a);
+    } else {
+        *p = a;
+    }
+}
 
 // ---------------------------------------------------------------- butterflies
 // In-register DFT of length R, natural order in and out, sign e^{-} (forward) or e^{+} (inverse).
@@ -262,12 +280,11 @@ struct RowPitch {
     static constexpr int value = L + L / P + 1;
 };
 
-template <int M, int P, int ROWS>
+template <int M, int P, int ROWS, bool XS = true>
 __device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane, float2* __restrict__ out_plane, int N,
                                              int row0, float2* lds, const float2* __restrict__ twL,
-                                             const float2* __restrict__ twM) {
+                                             const float2* __restrict__ twM, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
-    const int tid = threadIdx.x;
     const int t = tid % T, r = tid / T;
     float2* s = lds + r * PITCH;
     const float2* src = reinterpret_cast<const float2*>(in_plane + (size_t)(row0 + r) * M);
@@ -295,17 +312,16 @@ __device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane,
             const float2 O = make_float2(D.y, -D.x);  // (Z - conj Zm) / (2i)
             X = cadd(E, cmul(twM[k], O));
         }
-        st_stream(dst + (size_t)k * N, X);
+        st_x<XS>(dst + (size_t)k * N, X);
     }
 }
 
 // packed column-major spectra -> real rows, out = scale * unnormalised inverse
-template <int M, int P, int ROWS>
+template <int M, int P, int ROWS, bool XS = true>
 __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane, float* __restrict__ out_plane, int N,
                                              int row0, float2* lds, const float2* __restrict__ twL,
-                                             const float2* __restrict__ twM, float scale) {
+                                             const float2* __restrict__ twM, float scale, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
-    const int tid = threadIdx.x;
     {
         const int r2 = tid % ROWS, kk = tid / ROWS;
         float2* s2 = lds + r2 * PITCH;
@@ -313,7 +329,7 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int k = kk + T * i;
-            s2[k] = ld_stream(src + (size_t)k * N);
+            s2[k] = ld_x<XS>(src + (size_t)k * N);
         }
     }
     __syncthreads();
@@ -355,9 +371,9 @@ struct ColScratch {
 // X = scale * colFFT(a panel); column 0's spectrum is also left in the mirror buffer.
 template <int N, int P, int PW>
 __device__ __forceinline__ void col_fwd_setup(const float2* __restrict__ a_img, int col0, float2 (&xh)[P], float2* lds,
-                                              float scale, const float2* __restrict__ twN) {
+                                              float scale, const float2* __restrict__ twN, const int tid) {
     constexpr int T = N / P;
-    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int t = tid % T, c = tid / T;
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
     float2* smir = lds + PW * ColScratch<N, P>::value;
@@ -373,12 +389,12 @@ __device__ __forceinline__ void col_fwd_setup(const float2* __restrict__ a_img, 
 }
 
 // out panel = colIFFT(filter_k (.) X); packed column 0 uses alpha X(m) + beta conj X(-m).
-template <int N, int P, int PW, bool REAL>
+template <int N, int P, int PW, bool REAL, bool XS = true>
 __device__ __forceinline__ void col_fwd_emit(const float2 (&xh)[P], const void* __restrict__ filt, int k, int L,
                                              int col0, float2* __restrict__ out_plane, float2* lds,
-                                             const float2* __restrict__ twN) {
+                                             const float2* __restrict__ twN, const int tid) {
     constexpr int T = N / P;
-    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int t = tid % T, c = tid / T;
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
     const float2* smir = lds + PW * ColScratch<N, P>::value;
@@ -398,22 +414,22 @@ __device__ __forceinline__ void col_fwd_emit(const float2 (&xh)[P], const void* 
     fft<N, P, true>(y, s, t, twN);
     float2* o = out_plane + (size_t)col * N;
 #pragma unroll
-    for (int q = 0; q < P; ++q) st_stream(o + t + T * q, y[q]);
+    for (int q = 0; q < P; ++q) st_x<XS>(o + t + T * q, y[q]);
 }
 
 // acc += filter_k (.) colFFT(u panel); packed column 0 also accumulates g for the mirrored term.
-template <int N, int P, int PW, bool REAL>
+template <int N, int P, int PW, bool REAL, bool XS = true>
 __device__ __forceinline__ void col_inv_accum(const float2* __restrict__ u_plane, const void* __restrict__ filt, int k,
                                               int L, int col0, float2 (&acc)[P], float2 (&g)[P], float2* lds,
-                                              const float2* __restrict__ twN) {
+                                              const float2* __restrict__ twN, const int tid) {
     constexpr int T = N / P;
-    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int t = tid % T, c = tid / T;
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
     const float2* u = u_plane + (size_t)col * N;
     float2 x[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) x[q] = ld_stream(u + t + T * q);
+    for (int q = 0; q < P; ++q) x[q] = ld_x<XS>(u + t + T * q);
     fft<N, P, false>(x, s, t, twN);
     const size_t fstride = (size_t)(L + 1) * N;
     const size_t fbase = (size_t)k * fstride + (size_t)col * N;
@@ -429,9 +445,9 @@ __device__ __forceinline__ void col_inv_accum(const float2* __restrict__ u_plane
 // v panel = colIFFT(acc + [column 0: conj g(-m)])
 template <int N, int P, int PW>
 __device__ __forceinline__ void col_inv_finish(float2 (&acc)[P], const float2 (&g)[P], int col0, float2* __restrict__ v_img,
-                                               float2* lds, const float2* __restrict__ twN) {
+                                               float2* lds, const float2* __restrict__ twN, const int tid) {
     constexpr int T = N / P;
-    const int t = threadIdx.x % T, c = threadIdx.x / T;
+    const int t = tid % T, c = tid / T;
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
     float2* smir = lds + PW * ColScratch<N, P>::value;
@@ -467,7 +483,7 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(con
     const int nrb = N / RB;
     const int plane = blockIdx.x / nrb;
     const int row0 = (blockIdx.x % nrb) * RB;
-    row_r2c_tile<M, Pts<L>::value, RB>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM);
+    row_r2c_tile<M, Pts<L>::value, RB>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM, (int)threadIdx.x);
 }
 
 template <int M, int TAG>
@@ -482,7 +498,7 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(con
     const int plane = blockIdx.x / nrb;
     const int row0 = (blockIdx.x % nrb) * RB;
     row_c2r_tile<M, Pts<L>::value, RB>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL, twM,
-                                       scale);
+                                       scale, (int)threadIdx.x);
 }
 
 template <int N, int PW>
@@ -503,9 +519,9 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const flo
     extern __shared__ float2 lds[];
     const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
     float2 xh[P];
-    col_fwd_setup<N, P, PW>(A + (size_t)b * L * N, pan * PW, xh, lds, scale, twN);
+    col_fwd_setup<N, P, PW>(A + (size_t)b * L * N, pan * PW, xh, lds, scale, twN, (int)threadIdx.x);
     for (int k = 0; k < K; ++k)
-        col_fwd_emit<N, P, PW, REAL>(xh, filt, k, L, pan * PW, Tout + ((size_t)b * K + k) * L * N, lds, twN);
+        col_fwd_emit<N, P, PW, REAL>(xh, filt, k, L, pan * PW, Tout + ((size_t)b * K + k) * L * N, lds, twN, (int)threadIdx.x);
 }
 
 template <int N, int PW, bool REAL>
@@ -520,59 +536,97 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const flo
 #pragma unroll
     for (int q = 0; q < P; ++q) acc[q] = g[q] = make_float2(0.0f, 0.0f);
     for (int k = 0; k < K; ++k)
-        col_inv_accum<N, P, PW, REAL>(U + ((size_t)b * K + k) * L * N, filt, k, L, pan * PW, acc, g, lds, twN);
-    col_inv_finish<N, P, PW>(acc, g, pan * PW, V + (size_t)b * L * N, lds, twN);
+        col_inv_accum<N, P, PW, REAL>(U + ((size_t)b * K + k) * L * N, filt, k, L, pan * PW, acc, g, lds, twN, (int)threadIdx.x);
+    col_inv_finish<N, P, PW>(acc, g, pan * PW, V + (size_t)b * L * N, lds, twN, (int)threadIdx.x);
 }
 
-// ---------------------------------------------------------------- fused persistent kernels
+// ---------------------------------------------------------------- XCD-local persistent kernels
 // One cooperative launch per transform direction fuses the column stage and
-// the coefficient row stage. Work is cut into tasks on an (image, filter)
-// plane: column tasks (one panel of PW columns, looping over all K filters)
-// and row tasks (ROWS rows of one plane). Each plane is exchanged between the
-// two stages through one slot of a small ring (S slots per image in flight),
-// so the exchange stays on chip-side caches instead of making a full round
-// trip through HBM. Tasks live on Q logical queues (queue = block id mod Q);
-// an image's tasks all go to one queue, so with round-robin block placement
-// its exchange slots are produced and consumed within one XCD.
+// the coefficient row stage, and hands each (image, filter) plane from one
+// stage to the other through a small ring of exchange slots that stays in the
+// L2 of one XCD. The L2 is the coherence point of the compute units of an XCD
+// but not across XCDs, so every slot is produced and consumed by blocks of one
+// XCD: each block reads the id of the XCD it runs on (hardware register
+// XCC_ID), and takes work only from that XCD's queue.
 //
-// Ordering: a producer drains its wave's memory operations, the block
-// barriers, and one thread publishes with an agent-scope release increment;
-// a consumer's thread spins on a relaxed agent-scope load, then issues an
-// agent-scope acquire fence before the block barrier. Queue order lists every
-// task after the tasks it waits on, except the long column tasks, which are
-// dequeued first in their group; the host keeps their number below the blocks
-// per queue, so row tasks always find blocks. Every spin is bounded: on
-// timeout it raises an abort flag that makes all other waits give up, so the
-// kernel always drains; the host reports the flag through shear_check.
+// Start-up census: every block counts itself on its XCD and on a launch-wide
+// arrival counter, then waits until all blocks of the (co-resident) grid have
+// arrived. The XCDs that hold blocks, in id order, are the queues; image b goes
+// to queue b mod Q.
+//
+// Tasks of a queue, in dequeue order, per group of GI images: the GI x npan
+// column tasks (one panel of PW columns of one image, looping over all K
+// filters), then the K x GI x nrb row tasks (ROWS rows of one plane), filter
+// major. Image i of a group uses the slots i*S .. i*S+S-1 of its queue, filter
+// k the slot k mod S; a slot's uses are numbered across the groups
+// (generation), and each slot counts the column and the row tasks that have
+// finished with it.
+//
+// Ordering within an XCD: a finishing task waits for its own loads and stores
+// (stores are acknowledged by the L2), passes a block barrier, and one thread
+// adds to the slot's counter with a relaxed atomic. A waiting task polls the
+// counter with relaxed atomic loads, invalidates its compute unit's L1 with an
+// acquire fence, and passes a block barrier. No L2 write-back is needed
+// because producer and consumer share the L2; kernel boundaries order
+// everything else (inputs, outputs, counters).
+//
+// Progress: a task waits only on tasks dequeued before it, except the column
+// tasks of a group, which wait on the row tasks after them; their number
+// (GI x npan) must stay below the blocks of the queue, which the census
+// checks. Every wait is bounded: on timeout it raises an abort flag that makes
+// every other wait give up, so the kernel always drains; the host reports the
+// flag through shear_check.
 
 constexpr int SPIN_LIMIT = 1 << 18;
+constexpr int kMaxXcc = 16;  // XCC_ID values are taken modulo this
+
+// counter words of a launch: census, arrival, abort flag, queue heads, then
+// two counters (column side, row side) per slot
+constexpr int CTR_CENSUS = 0;
+constexpr int CTR_ARRIVED = kMaxXcc;
+constexpr int CTR_ABORT = kMaxXcc + 1;
+constexpr int CTR_HEADS = kMaxXcc + 2;
+constexpr int CTR_DONE = 2 * kMaxXcc + 2;
+
+__device__ __forceinline__ unsigned xcc_id() {
+    // hardware register 20 (XCC_ID): bits [3:0] are the XCD of the wave
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & (kMaxXcc - 1);
+}
+
+__device__ __forceinline__ unsigned ld_relaxed(unsigned* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ bool spin_geq(unsigned* ctr, unsigned target, unsigned* abort_flag) {
     for (int it = 0; it < SPIN_LIMIT; ++it) {
-        if (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) {
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            return true;
-        }
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) return false;
+        if (ld_relaxed(ctr) >= target) return true;
+        if (ld_relaxed(abort_flag) != 0u) return false;
         __builtin_amdgcn_s_sleep(2);
     }
     __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return false;
 }
 
-// Block-wide wait until *ctr >= target. All threads call it; returns false on abort.
+// Block-wide wait until *ctr >= target (all threads call it); false on abort.
+// Lines of the slot from an earlier generation may still sit in this compute
+// unit's L1: after the counter is reached, an agent-scope acquire invalidates
+// the L1 (the block's waves share it) before the barrier releases the block.
 __device__ __forceinline__ bool block_wait(unsigned* ctr, unsigned target, unsigned* abort_flag, int* sh_ok) {
-    if (threadIdx.x == 0) *sh_ok = spin_geq(ctr, target, abort_flag) ? 1 : 0;
+    if (threadIdx.x == 0) {
+        const bool ok = spin_geq(ctr, target, abort_flag);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *sh_ok = ok ? 1 : 0;
+    }
     __syncthreads();
     return *sh_ok != 0;
 }
 
-// Block-wide publish: every wave's loads and stores complete, then one agent-scope release increment.
+// Block-wide publish: every wave's loads and stores complete, then one relaxed increment.
 __device__ __forceinline__ void block_signal(unsigned* ctr) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int N, int M, int PC, int PW, int PR>
@@ -593,57 +647,92 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS), 4) void k_fu
     using C = FusedCfg<N, M, PC, PW, PR>;
     constexpr int L = C::L, ROWS = C::ROWS;
     extern __shared__ float2 lds[];
-    __shared__ int sh_task, sh_ok;
-    const int q = blockIdx.x % g.Q;
-    const int nq = (q < g.B) ? (g.B - q + g.Q - 1) / g.Q : 0;
+    __shared__ int sh_task, sh_ok, sh_q, sh_nq;
+    unsigned* ctr = bf.ctr;
+    unsigned* abort_flag = ctr + CTR_ABORT;
+    unsigned* heads = ctr + CTR_HEADS;
+    unsigned* done = ctr + CTR_DONE;  // slot s: [2s] column side, [2s+1] row side
+
+    // ---------------- census
+    if (threadIdx.x == 0) {
+        const unsigned x = xcc_id();
+        __hip_atomic_fetch_add(ctr + CTR_CENSUS + x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(ctr + CTR_ARRIVED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = spin_geq(ctr + CTR_ARRIVED, gridDim.x, abort_flag) ? 1 : 0;
+        int rank = 0, nq = 0;
+        unsigned mine = 0;
+        for (unsigned y = 0; y < (unsigned)kMaxXcc; ++y) {
+            const unsigned c = ld_relaxed(ctr + CTR_CENSUS + y);
+            if (c != 0u) {
+                rank += (y < x) ? 1 : 0;
+                ++nq;
+            }
+            if (y == x) mine = c;
+        }
+        // the column tasks of a group must leave blocks for its row tasks; the slots exist for Qmax queues
+        if (ok && (mine <= (unsigned)(g.GI * g.npan) || nq > g.Qmax)) {
+            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok = 0;
+        }
+        sh_ok = ok;
+        sh_q = rank;
+        sh_nq = nq;
+    }
+    __syncthreads();
+    if (!sh_ok) return;
+    const int q = sh_q, Q = sh_nq;
+    const int nimg = (q < g.B) ? (g.B - q + Q - 1) / Q : 0;  // images b = q + Q j of this queue
     const int per_img = g.npan + g.K * g.nrb;
-    const int total = nq * per_img;
+    const int total = nimg * per_img;
     const int FG = g.GI * per_img;
-    const int nslots = g.Q * g.ng * g.GI * g.S;
-    unsigned* done = bf.ctr;  // slot s: [2s] column-side count, [2s+1] row-side count
-    unsigned* heads = bf.ctr + 2 * nslots;
-    unsigned* abort_flag = heads + g.Q;
     const size_t plane = (size_t)L * N;
+    const size_t img = (size_t)N * M;
+    float2* qslots = bf.slots + (size_t)q * g.GI * g.S * plane;
+    unsigned* qdone = done + 2 * q * g.GI * g.S;
+
     for (;;) {
         __syncthreads();  // the previous task's LDS and shared reads are finished
-        if (threadIdx.x == 0) sh_task = (int)atomicAdd(&heads[q], 1u);
+        if (threadIdx.x == 0) sh_task = (int)__hip_atomic_fetch_add(&heads[q], 1u, __ATOMIC_RELAXED,
+                                                                     __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
         const int task = sh_task;
         if (task >= total) return;
+        // an opaque copy of the thread index per task keeps the tiles' address
+        // arithmetic inside the task instead of live across the task loop
+        int tid = (int)threadIdx.x;
+        asm volatile("" : "+v"(tid));
         const int grp = task / FG, rem = task % FG;
-        const int gi = min(g.GI, nq - grp * g.GI);
-        const int sbase0 = (q * g.ng + grp) * g.GI * g.S;
+        const int gi = min(g.GI, nimg - grp * g.GI);
         if (rem < gi * g.npan) {
-            // ---------------- column task: panel p of image i, all K planes
+            // ---------------- column task: panel p of image i of the group, all K planes
             const int i = rem / g.npan, p = rem % g.npan;
-            const int b = q + g.Q * (grp * g.GI + i);
-            const int sbase = sbase0 + i * g.S;
+            const int b = q + Q * (grp * g.GI + i);
             if constexpr (FWD) {
                 float2 xh[PC];
-                col_fwd_setup<N, PC, PW>(bf.A + (size_t)b * plane, p * PW, xh, lds, bf.scale, bf.twN);
+                col_fwd_setup<N, PC, PW>(bf.A + (size_t)b * plane, p * PW, xh, lds, bf.scale, bf.twN, tid);
                 for (int k = 0; k < g.K; ++k) {
-                    const int sid = sbase + k % g.S;
-                    const unsigned u = (unsigned)(k / g.S);
-                    // the slot's previous plane must have been read by all its row tiles
-                    if (u > 0 && !block_wait(&done[2 * sid + 1], u * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
-                    col_fwd_emit<N, PC, PW, REAL>(xh, bf.filt, k, L, p * PW, bf.slots + (size_t)sid * plane, lds,
-                                                  bf.twN);
-                    block_signal(&done[2 * sid]);
+                    const int s = k % g.S, sl = i * g.S + s;
+                    const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
+                    // the slot's previous plane must have been read by all its row tasks
+                    if (gen > 0 && !block_wait(&qdone[2 * sl + 1], gen * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
+                    col_fwd_emit<N, PC, PW, REAL, false>(xh, bf.filt, k, L, p * PW, qslots + (size_t)sl * plane, lds,
+                                                         bf.twN, tid);
+                    block_signal(&qdone[2 * sl]);
                 }
             } else {
                 float2 acc[PC], gg[PC];
 #pragma unroll
                 for (int qq = 0; qq < PC; ++qq) acc[qq] = gg[qq] = make_float2(0.0f, 0.0f);
                 for (int k = 0; k < g.K; ++k) {
-                    const int sid = sbase + k % g.S;
-                    const unsigned u = (unsigned)(k / g.S);
-                    // the plane's row tiles must all be written
-                    if (!block_wait(&done[2 * sid + 1], (u + 1) * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
-                    col_inv_accum<N, PC, PW, REAL>(bf.slots + (size_t)sid * plane, bf.filt, k, L, p * PW, acc, gg, lds,
-                                                   bf.twN);
-                    block_signal(&done[2 * sid]);
+                    const int s = k % g.S, sl = i * g.S + s;
+                    const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
+                    // all row tasks of the plane must have written the slot
+                    if (!block_wait(&qdone[2 * sl + 1], (gen + 1) * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
+                    col_inv_accum<N, PC, PW, REAL, false>(qslots + (size_t)sl * plane, bf.filt, k, L, p * PW, acc, gg,
+                                                          lds, bf.twN, tid);
+                    block_signal(&qdone[2 * sl]);
                 }
-                col_inv_finish<N, PC, PW>(acc, gg, p * PW, bf.V + (size_t)b * plane, lds, bf.twN);
+                col_inv_finish<N, PC, PW>(acc, gg, p * PW, bf.V + (size_t)b * plane, lds, bf.twN, tid);
             }
         } else {
             // ---------------- row task: tile r of plane (i, k)
@@ -651,22 +740,21 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS), 4) void k_fu
             const int k = r2 / (gi * g.nrb);
             const int i = (r2 / g.nrb) % gi;
             const int r = r2 % g.nrb;
-            const int b = q + g.Q * (grp * g.GI + i);
-            const int sid = sbase0 + i * g.S + k % g.S;
-            const unsigned u = (unsigned)(k / g.S);
-            const size_t img = (size_t)N * M;
+            const int b = q + Q * (grp * g.GI + i);
+            const int s = k % g.S, sl = i * g.S + s;
+            const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
             if constexpr (FWD) {
-                // all column panels of this plane must be written
-                if (!block_wait(&done[2 * sid], (u + 1) * (unsigned)g.npan, abort_flag, &sh_ok)) return;
-                row_c2r_tile<M, PR, ROWS>(bf.slots + (size_t)sid * plane, bf.cout + ((size_t)b * g.K + k) * img, N,
-                                          r * ROWS, lds, bf.twL, bf.twM, 1.0f);
+                // all column tasks must have written the plane
+                if (!block_wait(&qdone[2 * sl], (gen + 1) * (unsigned)g.npan, abort_flag, &sh_ok)) return;
+                row_c2r_tile<M, PR, ROWS, false>(qslots + (size_t)sl * plane, bf.cout + ((size_t)b * g.K + k) * img, N,
+                                                 r * ROWS, lds, bf.twL, bf.twM, 1.0f, tid);
             } else {
-                // the slot's previous plane must have been read by all column panels
-                if (u > 0 && !block_wait(&done[2 * sid], u * (unsigned)g.npan, abort_flag, &sh_ok)) return;
-                row_r2c_tile<M, PR, ROWS>(bf.cin + ((size_t)b * g.K + k) * img, bf.slots + (size_t)sid * plane, N,
-                                          r * ROWS, lds, bf.twL, bf.twM);
+                // the slot's previous plane must have been read by all column tasks
+                if (gen > 0 && !block_wait(&qdone[2 * sl], gen * (unsigned)g.npan, abort_flag, &sh_ok)) return;
+                row_r2c_tile<M, PR, ROWS, false>(bf.cin + ((size_t)b * g.K + k) * img, qslots + (size_t)sl * plane, N,
+                                                 r * ROWS, lds, bf.twL, bf.twM, tid);
             }
-            block_signal(&done[2 * sid + 1]);
+            block_signal(&qdone[2 * sl + 1]);
         }
     }
 }
@@ -695,10 +783,10 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
         const int i = task / (a.kg * a.npan);
         const int b = a.col_b0 + i;
         float2 xh[PC];
-        col_fwd_setup<N, PC, PW>(a.A + (size_t)b * plane, p * PW, xh, lds, a.scale, a.twN);
+        col_fwd_setup<N, PC, PW>(a.A + (size_t)b * plane, p * PW, xh, lds, a.scale, a.twN, (int)threadIdx.x);
         const int k1 = min(a.K, (g + 1) * a.kper);
         for (int k = g * a.kper; k < k1; ++k)
-            col_fwd_emit<N, PC, PW, REAL>(xh, a.filt, k, L, p * PW, a.bufC + ((size_t)i * a.K + k) * plane, lds, a.twN);
+            col_fwd_emit<N, PC, PW, REAL>(xh, a.filt, k, L, p * PW, a.bufC + ((size_t)i * a.K + k) * plane, lds, a.twN, (int)threadIdx.x);
         return;
     }
     task -= ncol;
@@ -707,7 +795,7 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
     const int i = task / (a.nrb * a.K);
     const int b = a.row_b0 + i;
     row_c2r_tile<M, PR, ROWS>(a.bufR + ((size_t)i * a.K + k) * plane, a.cout + ((size_t)b * a.K + k) * N * M, N,
-                              r * ROWS, lds, a.twL, a.twM, 1.0f);
+                              r * ROWS, lds, a.twL, a.twM, 1.0f, (int)threadIdx.x);
 }
 
 template <int N, int M, int PC, int PW, int PR, bool REAL>
@@ -729,7 +817,7 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
         const int k1 = min(a.K, (g + 1) * a.kper);
         for (int k = g * a.kper; k < k1; ++k)
             col_inv_accum<N, PC, PW, REAL>(a.bufC + ((size_t)i * a.K + k) * plane, a.filt, k, L, p * PW, acc, gg, lds,
-                                           a.twN);
+                                           a.twN, (int)threadIdx.x);
         // partial spectrum of filter group g (and, for packed column 0, its mirrored-term partial)
         const int t = threadIdx.x % TC, c = threadIdx.x / TC;
         const int col = p * PW + c;
@@ -749,7 +837,7 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
     const int i = task / (a.nrb * a.K);
     const int b = a.row_b0 + i;
     row_r2c_tile<M, PR, ROWS>(a.cin + ((size_t)b * a.K + k) * N * M, a.bufR + ((size_t)i * a.K + k) * plane, N,
-                              r * ROWS, lds, a.twL, a.twM);
+                              r * ROWS, lds, a.twL, a.twM, (int)threadIdx.x);
 }
 
 // V[b] panel p = colIFFT( sum_g partial_g  [+ conj of the mirrored column-0 partials] ), g in order
@@ -775,7 +863,7 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
             for (int q = 0; q < PC; ++q) gg[q] = cadd(gg[q], sg[t + TC * q]);
         }
     }
-    col_inv_finish<N, PC, PW>(acc, gg, p * PW, a.V + (size_t)b * plane, lds, a.twN);
+    col_inv_finish<N, PC, PW>(acc, gg, p * PW, a.V + (size_t)b * plane, lds, a.twN, (int)threadIdx.x);
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {

@@ -52,7 +52,8 @@ struct shear_system {
     // fused persistent path
     bool fused = false;           // selected and supported
     int cus = 0;                  // compute units
-    int fused_slots = 3;          // ring slots per image in flight
+    int fused_slots = 2;          // ring slots per image in flight
+    int fused_group = 0;          // images per group (0: automatic)
     shear::FusedInfo finfo[2];    // [0] forward, [1] inverse
     size_t abort_off = 0;         // byte offset of the abort flag in ws (last fused call)
     bool abort_valid = false;
@@ -62,7 +63,8 @@ namespace {
 
 thread_local std::string g_err;
 
-constexpr int kQueues = 8;  // logical work queues of the fused kernels (one per XCD)
+constexpr int kQueues = 8;  // XCDs the fused path sizes its slots and groups for (the kernel counts them)
+constexpr size_t kL2Budget = (size_t)2 << 20;  // exchange slots per XCD
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -263,31 +265,33 @@ bool fused_geom(const shear_system* s, bool fwd, int batch, shear::FusedGeom& g,
     if (fi.blocks_per_cu < 1) return false;
     grid = fi.blocks_per_cu * s->cus;
     const int per_queue = grid / kQueues;
-    // long column tasks of one group may hold at most half of a queue's blocks
-    int gi = (per_queue / 2) / fi.npan;
+    const size_t pb = plane_bytes(s);
+    const int S = std::max(1, std::min(s->fused_slots, s->K));
+    // long column tasks of one group may hold at most half of a queue's blocks,
+    // and a queue's slots should fit in half of its XCD's L2
+    int gi = std::min((per_queue / 2) / fi.npan, (int)(kL2Budget / ((size_t)S * pb)));
+    if (s->fused_group > 0) gi = std::min(s->fused_group, (per_queue - 1) / fi.npan);
     if (gi < 1) return false;
     const int nq_max = (batch + kQueues - 1) / kQueues;
-    gi = std::min(gi, nq_max);
     g.B = batch;
     g.K = s->K;
     g.L = s->cols / 2;
     g.N = s->rows;
-    g.Q = kQueues;
-    g.GI = gi;
-    g.S = std::max(1, std::min(s->fused_slots, s->K));
-    g.ng = (nq_max + gi - 1) / gi;
+    g.GI = std::min(gi, nq_max);
+    g.S = S;
+    g.Qmax = kQueues;
     g.npan = fi.npan;
     g.nrb = fi.nrb;
     return true;
 }
 
-size_t fused_slot_planes(const shear::FusedGeom& g) { return (size_t)g.Q * g.ng * g.GI * g.S; }
-size_t fused_ctr_words(const shear::FusedGeom& g) { return 2 * fused_slot_planes(g) + g.Q + 1; }
+size_t fused_slot_planes(const shear::FusedGeom& g) { return (size_t)g.Qmax * g.GI * g.S; }
 
 // Workspace layout of a fused call: [batch planes A or V][ring slots][counters].
 size_t fused_ws_needed(const shear_system* s, const shear::FusedGeom& g) {
     const size_t pb = plane_bytes(s);
-    return (size_t)g.B * pb + fused_slot_planes(g) * pb + ((fused_ctr_words(g) * sizeof(unsigned) + 255) & ~(size_t)255);
+    return (size_t)g.B * pb + fused_slot_planes(g) * pb +
+           ((shear::fused_ctr_words(g) * sizeof(unsigned) + 255) & ~(size_t)255);
 }
 
 // Images per chunk of the K-expanded intermediate, or 0 if even one does not fit.
@@ -516,12 +520,12 @@ int inverse_like(shear_system* s, const float* coeffs, float* x, int batch, void
             bf.twN = d.twN;
             bf.twL = d.twL;
             bf.twM = d.twM;
-            const int nw = (int)fused_ctr_words(g);
+            const int nw = (int)shear::fused_ctr_words(g);
             hipError_t e = shear::launch_zero_u32(bf.ctr, nw, st);
             if (e != hipSuccess) return hip_fail(e, "counter reset launch");
             e = timed(s, SHEAR_KERNEL_FUSED_INV, st, [&] { return shear::launch_fused(s->finfo[1], g, bf, grid, st); });
             if (e != hipSuccess) return hip_fail(e, "fused inverse launch");
-            s->abort_off = (size_t)((char*)(bf.ctr + nw - 1) - base);
+            s->abort_off = (size_t)((char*)(bf.ctr + shear::fused_abort_word()) - base);
             s->abort_valid = true;
             e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
                       [&] { return shear::launch_rows_c2r(d, bf.V, x, batch, 1.0f, false, st); });
@@ -753,8 +757,13 @@ int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_
     if (path == SHEAR_PATH_PIPELINE && !s->tiles.ok) return fail(SHEAR_E_SIZE, "no pipeline tiles for this size");
     s->path = path;
     s->fused = path == SHEAR_PATH_PERSISTENT;
-    if (chunk_images > 0) s->chunk_images = chunk_images;
-    if (filters_per_block > 0) s->filters_per_block = filters_per_block;
+    if (path == SHEAR_PATH_PERSISTENT) {
+        if (chunk_images > 0) s->fused_group = chunk_images;
+        if (filters_per_block > 0) s->fused_slots = filters_per_block;
+    } else {
+        if (chunk_images > 0) s->chunk_images = chunk_images;
+        if (filters_per_block > 0) s->filters_per_block = filters_per_block;
+    }
     return SHEAR_OK;
 }
 
@@ -800,12 +809,12 @@ int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, voi
             hipError_t e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st,
                                  [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
             if (e != hipSuccess) return hip_fail(e, "row r2c launch");
-            const int nw = (int)fused_ctr_words(g);
+            const int nw = (int)shear::fused_ctr_words(g);
             e = shear::launch_zero_u32(bf.ctr, nw, st);
             if (e != hipSuccess) return hip_fail(e, "counter reset launch");
             e = timed(s, SHEAR_KERNEL_FUSED_FWD, st, [&] { return shear::launch_fused(s->finfo[0], g, bf, grid, st); });
             if (e != hipSuccess) return hip_fail(e, "fused forward launch");
-            s->abort_off = (size_t)((char*)(bf.ctr + nw - 1) - base);
+            s->abort_off = (size_t)((char*)(bf.ctr + shear::fused_abort_word()) - base);
             s->abort_valid = true;
             return SHEAR_OK;
         }

@@ -312,8 +312,9 @@ def test_config4_256_k33_b32_sampled(gpu, lib):
                                      (1024, 1024, 4, 2), (512, 128, 2, 5)])
 def test_paths_agree(gpu, lib, N, M, J, B):
     """separate (default), pipeline and persistent paths: the forward transform is bitwise identical
-    (same per-element operations); the inverse of the persistent path is bitwise identical to the
-    separate path, the pipeline's (filter-group partial sums) agrees to rounding."""
+    (same per-element operations in the same order). The inverse sums the filters in the same order
+    on every path except the pipeline (filter-group partial sums), but the compiler may contract
+    multiply-adds differently in different kernels, so the inverses agree to rounding."""
     from paper_2006_04591_amd import ShearletSystem
 
     _say(f"case: paths {N}x{M} J={J} B={B}")
@@ -332,10 +333,13 @@ def test_paths_agree(gpu, lib, N, M, J, B):
         for path in ("pipeline", "persistent"):
             c1, y1, a1 = out[path]
             assert torch.equal(c0, c1), path
-        assert torch.equal(y0, out["persistent"][1]) and torch.equal(a0, out["persistent"][2])
-        assert _rel(out["pipeline"][1].cpu().numpy(), y0.cpu().numpy()) <= 1e-6
-        assert _rel(out["pipeline"][2].cpu().numpy(), a0.cpu().numpy()) <= 1e-6
-        assert _rel(out["pipeline"][1].cpu().numpy(), x.cpu().numpy()) <= TOL
+        for path in ("pipeline", "persistent"):
+            ey = _rel(out[path][1].cpu().numpy(), y0.cpu().numpy())
+            ea = _rel(out[path][2].cpu().numpy(), a0.cpu().numpy())
+            my = float((out[path][1] - y0).abs().max() / y0.abs().max())
+            print(f"{path}: inverse vs separate {ey:.2e} (max {my:.2e}), adjoint vs separate {ea:.2e}")
+            assert ey <= 1e-6 and ea <= 1e-6, path
+            assert _rel(out[path][1].cpu().numpy(), x.cpu().numpy()) <= TOL
 
 
 @pytest.mark.parametrize("chunk,fpb", [(1, 49), (3, 5), (16, 1), (5, 8)])
