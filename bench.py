@@ -27,8 +27,16 @@ if ROOT not in sys.path:
 METRIC = "fwd+inv shearlet Mpix·filters/s @512²×49 FP32; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 B, N, M, J = 16, 512, 512, 4
+SHEAR_LEVELS = [1, 1, 2, 2]
+CONFIG_ID = 2  # seeds of the synthetic images (synth.cartoon_batch config)
 SIGMA = 30.0
 WORKLOAD = "fwd+inv, 16 x 512x512 cartoon+N(0,30^2) images, 4 scales (shear levels 1,1,2,2) = 49 filters, FP32"
+METRIC_DENOISE = "denoise (fwd + hard threshold + inv) shearlet Mpix·filters/s @512²×49 FP32"
+METRIC_LAYER = "layer fwd+bwd (shear_forward + shear_adjoint) shearlet Mpix·filters/s @256²×33 FP32"
+WORKLOAD_LAYER = ("differentiable layer, forward and backward (upstream gradient N(0,1)), 32 x 1 x 256x256 "
+                  "cartoon images, 3 scales (shear levels 1,1,2) = 33 filters, FP32")
+WORKLOAD_DENOISE = ("hard-threshold denoising (thresholds 2.5/2.5/2.5/3.8 x sigma x RMS_k, low-pass kept), "
+                    "16 x 512x512 cartoon+N(0,30^2) images, 49 filters, FP32")
 
 
 def log(msg: str) -> None:
@@ -59,7 +67,23 @@ def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
         "pipe_fwd": filt + coef,
         "pipe_inv": coef + filt,
         "pipe_finish": 0,
+        "rows_thresh": 0,
     }[kind]
+
+
+def exchange_bytes(kind: str, K: int) -> float:
+    """Bytes of the packed exchange planes a kernel kind reads and writes per transform call
+    (the intermediates between the row and column stages)."""
+    plane = N * (M // 2) * 8
+    return {
+        "rows_r2c_images": B * plane,
+        "cols_fwd": B * plane + B * K * plane,
+        "rows_c2r_coeffs": B * K * plane,
+        "rows_r2c_coeffs": B * K * plane,
+        "cols_inv": B * K * plane + B * plane,
+        "rows_c2r_images": B * plane,
+        "rows_thresh": 2 * B * K * plane,
+    }.get(kind, 0.0)
 
 
 def path_algorithmic_bytes(K: int, real_filters: bool) -> float:
@@ -86,21 +110,30 @@ def traffic_from_profiles(kind: str, per_launch_units: float):
         return None
 
 
-def cpu_baseline(x_host, min_seconds: float, max_images: int) -> dict:
+def cpu_baseline(x_host, min_seconds: float, max_images: int, workload: str = "fwdinv") -> dict:
     """The FP64 oracle (numpy, as it stands) on a bounded sample of the same workload:
-    fwd+inv of the batch images in order (cycling), until min_seconds have elapsed."""
+    fwd+inv (or denoising) of the batch images in order (cycling), until min_seconds have elapsed."""
     import numpy as np
 
+    from oracle import apps as OA
     from oracle import filters as OF
     from oracle import transform as OT
 
-    log(f"cpu baseline: oracle system build 512x512 J={J}")
+    log(f"cpu baseline: oracle system build {N}x{M} J={J}")
     ref = OF.build_system(N, M, J)
+    thr = OA.thresholds(ref.idx, ref.rms, SIGMA)
     t0 = time.perf_counter()
     n = 0
     while n < max_images:
-        c = OT.forward_plain(x_host[n % B].astype(np.float64), ref.spectra)
-        OT.inverse_plain(c, ref.spectra, ref.W)
+        xi = x_host[n % B].astype(np.float64)
+        if workload == "denoise":
+            OA.denoise(xi, ref.spectra, ref.W, thr)
+        elif workload == "layer":
+            c = OT.forward_plain(xi, ref.spectra)
+            OT.adjoint_plain(c, ref.spectra)
+        else:
+            c = OT.forward_plain(xi, ref.spectra)
+            OT.inverse_plain(c, ref.spectra, ref.W)
         n += 1
         dt = time.perf_counter() - t0
         if n % 4 == 0:
@@ -114,8 +147,9 @@ def cpu_baseline(x_host, min_seconds: float, max_images: int) -> dict:
         "unit": "Mpix·filters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"numpy FP64 oracle, fwd+inv of {n} images of the 512x512, 49-filter batch (cycling through "
-                  f"the 16), {dt:.1f} s; numpy.fft runs single-threaded",
+        "sample": f"numpy FP64 oracle, {dict(denoise='denoising', layer='forward+adjoint').get(workload, 'fwd+inv')} "
+                  f"of {n} images of the {N}x{M}, {ref.K}-filter batch (cycling through the {B}), {dt:.1f} s; "
+                  f"numpy.fft runs single-threaded",
     }
 
 
@@ -200,7 +234,16 @@ def main() -> int:
     ap.add_argument("--fpb", type=int, default=0, help="pipeline: filters per column block (0 = library default)")
     ap.add_argument("--chunk-images", type=int, default=0,
                     help="images per chunk of the K-expanded intermediate (0 = whole batch)")
+    ap.add_argument("--workload", default="fwdinv", choices=("fwdinv", "denoise", "layer"),
+                    help="fwdinv: shear_forward + shear_inverse (the headline); denoise: shear_denoise with the "
+                         "paper's thresholds (Section 4.2); layer: the autograd layer's forward and backward at "
+                         "32 x 256x256, 33 filters")
     args = ap.parse_args()
+    denoise = args.workload == "denoise"
+    layer = args.workload == "layer"
+    global B, N, M, J, SHEAR_LEVELS, CONFIG_ID
+    if layer:
+        B, N, M, J, SHEAR_LEVELS, CONFIG_ID = 32, 256, 256, 3, [1, 1, 2], 4
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); run with --gpus 1",
               file=sys.stderr)
@@ -216,7 +259,7 @@ def main() -> int:
         print("bench.py: no GPU visible", file=sys.stderr)
         return 2
     dev = torch.device("cuda:0")
-    log("bench: building system 512x512 J=4")
+    log(f"bench: building system {N}x{M} J={J}")
     t0 = time.perf_counter()
     cap = 0
     if args.chunk_images > 0:
@@ -229,15 +272,30 @@ def main() -> int:
     S, _ = shs.export_spectra()
     real_filters = bool(np.all(S.imag == 0))
     log(f"bench: K={K}, build {build_s:.2f} s, real filters={real_filters}")
-    x_host = synth.cartoon_batch(B, N, M, config=2, sigma=SIGMA)
+    x_host = synth.cartoon_batch(B, N, M, config=CONFIG_ID, sigma=0.0 if layer else SIGMA)
     x = torch.from_numpy(x_host).to(dev)
     c = torch.empty((B, K, N, M), dtype=torch.float32, device=dev)
     y = torch.empty((B, N, M), dtype=torch.float32, device=dev)
     shs.reserve(B)
+    thr = torch.from_numpy(np.tile(shs.paper_thresholds(SIGMA), (B, 1))).to(dev)
+    if layer:
+        from paper_2006_04591_amd import ShearletLayer
+
+        net = ShearletLayer(N, M, J, system=shs)
+        xg = x[:, None].clone().requires_grad_(True)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(4)
+        g = torch.randn((B, K, N, M), generator=gen, device=dev, dtype=torch.float32)
 
     def step():
-        shs.forward(x, out=c)
-        shs.inverse(c, out=y)
+        if denoise:
+            shs.denoise(x, thr, out=y)
+        elif layer:
+            xg.grad = None
+            net(xg).backward(g)
+        else:
+            shs.forward(x, out=c)
+            shs.inverse(c, out=y)
 
     for i in range(args.warmup):
         step()
@@ -261,11 +319,36 @@ def main() -> int:
     ms_step = ms_total / args.steps
     log(f"bench: {args.steps} timed steps, {ms_step:.3f} ms/step")
 
-    # correctness guard on the timed output: reconstruction of the inputs
-    err = float(torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x))
-    if not err <= 1e-5:
-        print(f"bench.py: reconstruction error {err:.3e} exceeds 1e-5", file=sys.stderr)
-        return 1
+    quality = {}
+    err = None
+    if layer:
+        # the timed gradient is the adjoint of the upstream gradient (same kernels, so bitwise)
+        ref_grad = shs.adjoint(g)
+        torch.cuda.synchronize()
+        if not torch.equal(xg.grad[:, 0], ref_grad):
+            print("bench.py: layer gradient differs from shear_adjoint of the upstream gradient", file=sys.stderr)
+            return 1
+    elif denoise:
+        # the timed output against the clean images: PSNR = 20 log10(255 sqrt(pixels) / ||f - g||) (Section 4.2)
+        def psnr(f, g):
+            d = np.asarray(f, dtype=np.float64) - np.asarray(g, dtype=np.float64)
+            return float(20.0 * np.log10(255.0 * np.sqrt(d.size) / np.linalg.norm(d)))
+
+        clean = synth.cartoon_batch(B, N, M, config=CONFIG_ID, sigma=0.0)
+        yh = y.cpu().numpy()
+        p_out = [psnr(clean[b], yh[b]) for b in range(B)]
+        p_in = [psnr(clean[b], x_host[b]) for b in range(B)]
+        quality = {"psnr_denoised_mean_db": float(np.mean(p_out)), "psnr_noisy_mean_db": float(np.mean(p_in))}
+        if not np.all(np.isfinite(yh)) or quality["psnr_denoised_mean_db"] <= quality["psnr_noisy_mean_db"]:
+            print(f"bench.py: denoising did not improve the PSNR: {quality}", file=sys.stderr)
+            return 1
+        err = None
+    else:
+        # correctness guard on the timed output: reconstruction of the inputs
+        err = float(torch.linalg.vector_norm(y - x) / torch.linalg.vector_norm(x))
+        if not err <= 1e-5:
+            print(f"bench.py: reconstruction error {err:.3e} exceeds 1e-5", file=sys.stderr)
+            return 1
 
     units = B * N * M * K / 1e6
     value = units / (ms_step / 1e3)
@@ -275,21 +358,30 @@ def main() -> int:
             continue
         avg = tot / n
         ab = kernel_algorithmic_bytes(kind, K, real_filters) * args.steps / n  # per launch
+        xb = exchange_bytes(kind, K) * args.steps / n
         kernels[kind] = {"launches": n, "avg_ms": avg, "share": tot / ms_total, "algorithmic_bytes_per_launch": ab,
-                         "algorithmic_GBs": ab / (avg / 1e3) / 1e9}
+                         "algorithmic_GBs": ab / (avg / 1e3) / 1e9, "exchange_bytes_per_launch": xb,
+                         "exchange_GBs": xb / (avg / 1e3) / 1e9}
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
     dk = kernels[dom]
-    ab = dk["algorithmic_bytes_per_launch"]
+    if dk["algorithmic_bytes_per_launch"] > 0:
+        ab, basis = dk["algorithmic_bytes_per_launch"], "algorithmic"
+    else:
+        # the fused threshold kernel moves none of the method's inputs or outputs: its bytes are
+        # the exchange planes it reads and writes
+        ab, basis = dk["exchange_bytes_per_launch"], "exchange planes read + written"
     achieved = ab / (dk["avg_ms"] / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(dom, 1.0),
-                "kernel": dom, "avg_launch_ms": dk["avg_ms"], "algorithmic_bytes_per_launch": ab}
+                "kernel": dom, "avg_launch_ms": dk["avg_ms"], "bytes_per_launch": ab, "bytes_basis": basis}
     pb = path_algorithmic_bytes(K, real_filters)
+    if denoise:
+        pb = 2 * B * N * M * 4 + 2 * K * N * (M // 2 + 1) * (4 if real_filters else 8)  # x, y, two filter sets
     path = {"bound": "hbm", "achieved": pb / (ms_step / 1e3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": pb / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes_per_step": pb}
 
     out = {
-        "metric": METRIC,
+        "metric": METRIC_DENOISE if denoise else (METRIC_LAYER if layer else METRIC),
         "value": value,
         "unit": "Mpix·filters/s",
         "n_gpus": 1,
@@ -301,14 +393,20 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD, "batch": B, "rows": N, "cols": M, "filters": K, "shear_levels": [1, 1, 2, 2]},
+        "config": {"workload": WORKLOAD_DENOISE if denoise else (WORKLOAD_LAYER if layer else WORKLOAD), "batch": B,
+                   "rows": N, "cols": M, "filters": K, "shear_levels": SHEAR_LEVELS},
         "roofline": roofline,
         "path_roofline": path,
         "kernels": kernels,
-        "reconstruction_rel_err": err,
         "system_build_s": build_s,
     }
-    out["config"]["path"] = args.path
+    if denoise:
+        out.update(quality)
+        out["config"]["path"] = "separate (fused row threshold kernel)"
+    elif not layer:
+        out["reconstruction_rel_err"] = err
+    if not denoise:
+        out["config"]["path"] = args.path
     if args.chunk:
         out["config"]["pipeline_chunk_images"] = args.chunk
     if args.fpb:
@@ -316,7 +414,7 @@ def main() -> int:
     if args.chunk_images > 0:
         out["config"]["chunk_images"] = args.chunk_images
     if args.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_seconds, 64)
+        out["cpu_baseline"] = cpu_baseline(x_host, args.cpu_seconds, 64, args.workload)
     shs.close()
     print(json.dumps(out))
     return 0

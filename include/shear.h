@@ -123,6 +123,21 @@ int shear_inverse(shear_system* s, const float* coeffs, float* x, int batch, voi
  * <shear_forward(x), c> = <x, shear_adjoint(c)>. Asynchronous. */
 int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, void* hip_stream);
 
+/* Shearlet denoising by hard thresholding (Section 4.2): for each image,
+ *   y = SH^-1 T SH x,   (T c)(n) = c(n) if |c(n)| >= thresholds[b*K + k], else 0,
+ * with SH = shear_forward and SH^-1 = shear_inverse; the paper's rule for the
+ * thresholds is delta = K_j * sigma * RMS_k for a filter k of scale j.
+ * x, y: batch*rows*cols float32 (device; they may be the same buffer).
+ * thresholds: batch*K float32 (device), one per image and filter; a
+ * threshold <= 0 keeps every coefficient of its plane, +inf drops them all.
+ * kept: batch*K uint32 (device) or NULL; if given, it is cleared and receives
+ * the number of coefficients kept per plane. The thresholded coefficients are
+ * never written to memory: the threshold sits between the forward row stage
+ * and the inverse row stage of one kernel. Always runs the separate-launch
+ * kernels, whatever shear_set_path selected. Asynchronous. */
+int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
+                  void* hip_stream);
+
 /* Launch kinds reported by shear_profile_read (one kernel symbol each). */
 #define SHEAR_KERNEL_ROWS_R2C_IMAGES 0 /* forward: row FFT of the images              */
 #define SHEAR_KERNEL_COLS_FWD 1        /* forward: column FFT, x conj filter, IFFT (K-expanding) */
@@ -135,7 +150,8 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
 #define SHEAR_KERNEL_PIPE_FWD 8        /* forward, pipeline path: one chunk step (column + row stages) */
 #define SHEAR_KERNEL_PIPE_INV 9        /* inverse/adjoint, pipeline path: one chunk step */
 #define SHEAR_KERNEL_PIPE_FINISH 10    /* inverse/adjoint, pipeline path: sum of partial spectra + column IFFT */
-#define SHEAR_KERNEL_KINDS 11
+#define SHEAR_KERNEL_ROWS_THRESH 11    /* denoising: row inverse FFT, hard threshold, row FFT (in place) */
+#define SHEAR_KERNEL_KINDS 12
 
 /* Per-launch timing (tracing). While enabled, every kernel launch of the
  * system is bracketed by two hipEvents recorded on the caller's stream. */

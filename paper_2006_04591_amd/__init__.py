@@ -14,4 +14,7 @@ from ._binding import (
     load_library,
 )
 
-__all__ = ["EXPORTED", "LIB_PATH", "ShearError", "ShearletSystem", "design_spectra", "load_library"]
+from .autograd import ShearletLayer, ShearletTransform
+
+__all__ = ["EXPORTED", "LIB_PATH", "ShearError", "ShearletLayer", "ShearletSystem", "ShearletTransform",
+           "design_spectra", "load_library"]

@@ -35,6 +35,7 @@ EXPORTED = (
     "shear_forward",
     "shear_inverse",
     "shear_adjoint",
+    "shear_denoise",
     "shear_profile_enable",
     "shear_profile_read",
     "shear_set_path",
@@ -93,6 +94,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shear_workspace_bytes.argtypes = [P, I, ctypes.POINTER(ctypes.c_size_t)]
     for name in ("shear_forward", "shear_inverse", "shear_adjoint"):
         getattr(lib, name).argtypes = [P, P, P, I, P]
+    lib.shear_denoise.argtypes = [P, P, P, I, P, P, P]
     for name in EXPORTED:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
@@ -269,11 +271,55 @@ class ShearletSystem:
         """shear_adjoint: coefficients (B, K, rows, cols) -> images (B, rows, cols)."""
         return self._inv(self._lib.shear_adjoint, "shear_adjoint", coeffs, out, stream)
 
+    # ------------------------------------------------------------ denoising
+    def paper_thresholds(self, sigma: float, factors=None) -> np.ndarray:
+        """Per-filter thresholds of the denoising rule of Section 4.2, delta_k = K_j sigma RMS_k for a
+        filter k of scale j, with K_j = 2.5 except 3.8 on the finest scale unless ``factors`` (J values,
+        coarse to fine) are given; the low-pass (scale 0) gets 0, i.e. is kept. float32 (K,)."""
+        scale = self.idx[:, 1]
+        J = int(scale.max())
+        if factors is None:
+            factors = [2.5] * (J - 1) + [3.8]
+        f = np.asarray(factors, dtype=np.float64)
+        if f.shape != (J,):
+            raise ValueError(f"need {J} scale factors, got shape {f.shape}")
+        t = np.zeros(self.K, dtype=np.float64)
+        band = scale > 0
+        t[band] = f[scale[band] - 1] * float(sigma) * self.rms[band]
+        return t.astype(np.float32)
+
+    def denoise(self, x, thresholds, out=None, kept=False, stream=None):
+        """shear_denoise: y = SH^-1 T SH x with hard thresholds (B, K) or (K,) (float32, on x's device).
+        Returns y, or (y, kept counts (B, K) int64 tensor) when kept is True."""
+        import torch
+
+        B = x.shape[0]
+        self._check_tensor(x, (B, self.rows, self.cols), "x")
+        thr = torch.as_tensor(thresholds, dtype=torch.float32, device=x.device)
+        if thr.dim() == 1:
+            if thr.shape[0] != self.K:
+                raise ValueError(f"thresholds has {thr.shape[0]} entries, expected K = {self.K}")
+            thr = thr.expand(B, self.K)
+        thr = thr.contiguous()
+        self._check_tensor(thr, (B, self.K), "thresholds")
+        if out is None:
+            out = torch.empty((B, self.rows, self.cols), dtype=torch.float32, device=x.device)
+        self._check_tensor(out, (B, self.rows, self.cols), "out")
+        cnt = torch.empty((B, self.K), dtype=torch.int32, device=x.device) if kept else None
+        _check(self._lib.shear_denoise(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
+                                       ctypes.c_void_p(thr.data_ptr()),
+                                       ctypes.c_void_p(cnt.data_ptr()) if kept else None, _stream_ptr(stream)),
+               "shear_denoise")
+        if kept:
+            # the library writes uint32 counts; a plane has at most 2^20 coefficients
+            return out, cnt.to(torch.int64)
+        return out
+
     # ------------------------------------------------------------ execution path
     PATHS = {"pipeline": 0, "separate": 1, "persistent": 2}
 
     def set_path(self, path: str, chunk_images: int = 0, filters_per_block: int = 0) -> None:
-        """Execution path: "pipeline" (default where supported), "separate" or "persistent" (shear_set_path)."""
+        """Execution path: "separate" (default), "pipeline" or "persistent" (shear_set_path)."""
         _check(self._lib.shear_set_path(self._h, self.PATHS[path], int(chunk_images), int(filters_per_block)),
                "shear_set_path")
 
@@ -283,7 +329,7 @@ class ShearletSystem:
 
     # ------------------------------------------------------------ tracing
     KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images",
-                    "fused_fwd", "fused_inv", "pipe_fwd", "pipe_inv", "pipe_finish")
+                    "fused_fwd", "fused_inv", "pipe_fwd", "pipe_inv", "pipe_finish", "rows_thresh")
 
     def profile(self, on: bool = True) -> None:
         """Brackets every launch with hipEvents on the caller's stream (shear_profile_enable)."""

@@ -28,6 +28,10 @@ hipError_t launch_rows_r2c(const DevPlan& d, const float* in, float2* out, int p
 // out = scale * (unnormalised length-M inverse DFT of the Hermitian rows).
 hipError_t launch_rows_c2r(const DevPlan& d, const float2* in, float* out, int planes, float scale, bool coeff_planes,
                            hipStream_t st);
+// Coefficient row stages with a hard threshold between them, in place on
+// nplanes packed planes; thr[p] and kept[p] (kept may be null) per plane.
+hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
+                              hipStream_t st);
 
 // Forward transform, column stage, K-expanding: for each image of A (nimg x L x N),
 // X = scale * colFFT(A); for each filter k: T[b][k] = colIFFT(filt_k (.) X)

@@ -501,6 +501,106 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(con
                                        scale, (int)threadIdx.x);
 }
 
+// Forward row stage, hard threshold and inverse row stage of one tile of a
+// coefficient plane, in place on its packed column-major spectra: the rows
+// become real coefficients c (as the forward transform writes them), every
+// coefficient with |c| < thr is set to zero, and the thresholded rows are
+// transformed back, so thresholded coefficients never leave the chip. The
+// number of kept coefficients of the tile is added to *kept (when non-null).
+template <int M, int P, int ROWS>
+__device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int N, int row0, float2* lds,
+                                                const float2* __restrict__ twL, const float2* __restrict__ twM,
+                                                float thr, unsigned* __restrict__ kept, const int tid) {
+    constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
+    const int r2 = tid % ROWS, kk = tid / ROWS;
+    {
+        float2* s2 = lds + r2 * PITCH;
+        const float2* src = plane + row0 + r2;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int k = kk + T * i;
+            s2[k] = ld_stream(src + (size_t)k * N);
+        }
+    }
+    __syncthreads();
+    const int t = tid % T, r = tid / T;
+    float2* s = lds + r * PITCH;
+    float2 v[P];
+    {
+        const float2 P0 = s[0];
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const int k = t + T * q;
+            float2 X = s[k], Xm = s[(L - k) & (L - 1)];
+            if (k == 0) {
+                X = make_float2(P0.x, 0.0f);
+                Xm = make_float2(P0.y, 0.0f);
+            }
+            const float2 A = make_float2(X.x + Xm.x, X.y - Xm.y);
+            const float2 D = make_float2(X.x - Xm.x, X.y + Xm.y);
+            const float2 B = cmul(D, cconj(twM[k]));
+            v[q] = make_float2(A.x - B.y, A.y + B.x);
+        }
+    }
+    __syncthreads();
+    fft<L, P, true>(v, s, t, twL);
+    // v[q] holds the coefficients at columns 2(t + T q) and 2(t + T q) + 1
+    unsigned n = 0;
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        const bool kx = fabsf(v[q].x) >= thr, ky = fabsf(v[q].y) >= thr;
+        v[q] = make_float2(kx ? v[q].x : 0.0f, ky ? v[q].y : 0.0f);
+        n += (kx ? 1u : 0u) + (ky ? 1u : 0u);
+    }
+    fft<L, P, false>(v, s, t, twL);
+#pragma unroll
+    for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
+    __syncthreads();
+    {
+        const float2* s2 = lds + r2 * PITCH;
+        float2* dst = plane + row0 + r2;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            const int k = kk + T * i;
+            const float2 Z = s2[k];
+            const float2 Zm = s2[(L - k) & (L - 1)];
+            float2 X;
+            if (k == 0) {
+                X = make_float2(Z.x + Z.y, Z.x - Z.y);
+            } else {
+                const float2 E = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
+                const float2 D = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
+                const float2 O = make_float2(D.y, -D.x);
+                X = cadd(E, cmul(twM[k], O));
+            }
+            st_stream(dst + (size_t)k * N, X);
+        }
+    }
+    if (kept != nullptr) {
+        // sum over each wavefront (or the whole block, if smaller), then one atomic each
+        constexpr int WV = (ROWS * T < 64) ? ROWS * T : 64;
+#pragma unroll
+        for (int off = WV / 2; off >= 1; off >>= 1) n += __shfl_xor(n, off, WV);
+        if (tid % WV == 0) atomicAdd(kept, n);
+    }
+}
+
+// planes[p] for p < gridDim.x / (N / RB): threshold thr[p], kept counts kept[p]
+template <int M>
+__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_thresh(float2* __restrict__ planes, int N,
+                                                                              const float* __restrict__ thr,
+                                                                              unsigned* __restrict__ kept,
+                                                                              const float2* __restrict__ twL,
+                                                                              const float2* __restrict__ twM) {
+    constexpr int L = M / 2;
+    extern __shared__ float2 lds[];
+    const int nrb = N / RB;
+    const int plane = blockIdx.x / nrb;
+    const int row0 = (blockIdx.x % nrb) * RB;
+    row_thresh_tile<M, Pts<L>::value, RB>(planes + (size_t)plane * L * N, N, row0, lds, twL, twM, thr[plane],
+                                          kept ? kept + plane : nullptr, (int)threadIdx.x);
+}
+
 template <int N, int PW>
 struct ColCfg {
     static constexpr int P = Pts<N>::value;
@@ -901,6 +1001,19 @@ hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes
     return hipGetLastError();
 }
 
+template <int M>
+hipError_t rows_thresh_t(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
+                         hipStream_t st) {
+    constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
+    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
+    hipError_t e = set_lds(k_rows_thresh<M>, lds);
+    if (e != hipSuccess) return e;
+    const size_t blocks = (size_t)nplanes * (d.N / RB);
+    hipLaunchKernelGGL((k_rows_thresh<M>), dim3((unsigned)blocks), dim3(RB * T), lds, st, planes, d.N, thr, kept,
+                       d.twL, d.twM);
+    return hipGetLastError();
+}
+
 template <int N, int PW>
 hipError_t cols_fwd_t(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
                       hipStream_t st) {
@@ -980,6 +1093,20 @@ hipError_t launch_rows_r2c(const DevPlan& d, const float* in, float2* out, int p
 hipError_t launch_rows_c2r(const DevPlan& d, const float2* in, float* out, int planes, float scale, bool coeff_planes,
                            hipStream_t st) {
     return coeff_planes ? rows_c2r_sw<1>(d, in, out, planes, scale, st) : rows_c2r_sw<0>(d, in, out, planes, scale, st);
+}
+
+hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
+                              hipStream_t st) {
+    switch (d.M) {
+        case 16: return rows_thresh_t<16>(d, planes, nplanes, thr, kept, st);
+        case 32: return rows_thresh_t<32>(d, planes, nplanes, thr, kept, st);
+        case 64: return rows_thresh_t<64>(d, planes, nplanes, thr, kept, st);
+        case 128: return rows_thresh_t<128>(d, planes, nplanes, thr, kept, st);
+        case 256: return rows_thresh_t<256>(d, planes, nplanes, thr, kept, st);
+        case 512: return rows_thresh_t<512>(d, planes, nplanes, thr, kept, st);
+        case 1024: return rows_thresh_t<1024>(d, planes, nplanes, thr, kept, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 #define SHEAR_COLS_SWITCH(FN, ...)                                                 \

@@ -854,6 +854,48 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
     return inverse_like(s, coeffs, x, batch, stream, s ? s->filt_adj : nullptr);
 }
 
+int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
+                  void* stream) {
+    int rc = check_call(s, x, y, batch);
+    if (rc != SHEAR_OK) return rc;
+    if (!thresholds) return fail(SHEAR_E_INVALID, "thresholds pointer is NULL");
+    int chunk = 0;
+    if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
+    s->abort_valid = false;
+    const shear::DevPlan& d = s->plan;
+    hipStream_t st = (hipStream_t)stream;
+    const size_t pb = plane_bytes(s) / sizeof(float2);
+    float2* A = (float2*)s->ws;  // row spectra of the images, then (image by image) the summed spectra
+    float2* T = A + (size_t)batch * pb;
+    const size_t img = (size_t)d.N * d.M;
+    hipError_t e;
+    if (kept) {
+        e = shear::launch_zero_u32(kept, batch * d.K, st);
+        if (e != hipSuccess) return hip_fail(e, "kept-count reset launch");
+    }
+    e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st, [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
+    if (e != hipSuccess) return hip_fail(e, "row r2c launch");
+    const float scale = (float)(1.0 / (double)img);  // 1/(N M): a power of two, exact
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
+        e = timed(s, SHEAR_KERNEL_COLS_FWD, st,
+                  [&] { return shear::launch_cols_fwd(d, A + (size_t)b0 * pb, T, nb, s->filt_fwd, scale, st); });
+        if (e != hipSuccess) return hip_fail(e, "column pass launch");
+        e = timed(s, SHEAR_KERNEL_ROWS_THRESH, st, [&] {
+            return shear::launch_rows_thresh(d, T, nb * d.K, thresholds + (size_t)b0 * d.K,
+                                             kept ? kept + (size_t)b0 * d.K : nullptr, st);
+        });
+        if (e != hipSuccess) return hip_fail(e, "row threshold launch");
+        // the images of this chunk no longer need their row spectra: the sums replace them
+        e = timed(s, SHEAR_KERNEL_COLS_INV, st,
+                  [&] { return shear::launch_cols_inv(d, T, A + (size_t)b0 * pb, nb, s->filt_inv, st); });
+        if (e != hipSuccess) return hip_fail(e, "column pass launch");
+    }
+    e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st, [&] { return shear::launch_rows_c2r(d, A, y, batch, 1.0f, false, st); });
+    if (e != hipSuccess) return hip_fail(e, "row c2r launch");
+    return SHEAR_OK;
+}
+
 int shear_profile_enable(shear_system* s, int on) {
     if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
     s->prof_on = on != 0;
