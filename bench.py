@@ -35,7 +35,7 @@ METRIC_DENOISE = "denoise (fwd + hard threshold + inv) shearlet Mpix·filters/s 
 METRIC_LAYER = "layer fwd+bwd (shear_forward + shear_adjoint) shearlet Mpix·filters/s @256²×33 FP32"
 WORKLOAD_LAYER = ("differentiable layer, forward and backward (upstream gradient N(0,1)), 32 x 1 x 256x256 "
                   "cartoon images, 3 scales (shear levels 1,1,2) = 33 filters, FP32")
-WORKLOAD_DENOISE = ("hard-threshold denoising (thresholds 2.5/2.5/2.5/3.8 x sigma x RMS_k, low-pass kept), "
+WORKLOAD_DENOISE = ("hard-threshold denoising (threshold 3 x sigma x RMS_k per band, low-pass kept), "
                     "16 x 512x512 cartoon+N(0,30^2) images, 49 filters, FP32")
 
 
@@ -121,7 +121,7 @@ def cpu_baseline(x_host, min_seconds: float, max_images: int, workload: str = "f
 
     log(f"cpu baseline: oracle system build {N}x{M} J={J}")
     ref = OF.build_system(N, M, J)
-    thr = OA.thresholds(ref.idx, ref.rms, SIGMA)
+    thr = OA.thresholds(ref.idx, ref.rms, SIGMA, factors=[3.0] * J)
     t0 = time.perf_counter()
     n = 0
     while n < max_images:
@@ -277,7 +277,8 @@ def main() -> int:
     c = torch.empty((B, K, N, M), dtype=torch.float32, device=dev)
     y = torch.empty((B, N, M), dtype=torch.float32, device=dev)
     shs.reserve(B)
-    thr = torch.from_numpy(np.tile(shs.paper_thresholds(SIGMA), (B, 1))).to(dev)
+    # denoising workload: hard threshold 3 sigma RMS_k on every band, low-pass kept
+    thr = torch.from_numpy(np.tile(shs.paper_thresholds(SIGMA, factors=[3.0] * J), (B, 1))).to(dev)
     if layer:
         from paper_2006_04591_amd import ShearletLayer
 
