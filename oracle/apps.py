@@ -40,6 +40,7 @@ __all__ = [
     "denoise",
     "psnr",
     "delta_schedule",
+    "delta_schedule_linear",
     "inpaint",
 ]
 
@@ -106,20 +107,28 @@ def delta_schedule(delta_init: float, delta_min: float, iterations: int) -> np.n
     return out
 
 
+def delta_schedule_linear(delta_init: float, iterations: int) -> np.ndarray:
+    """A linear decay to zero over the iterations: delta_init (1 - i / (iterations - 1)), i < iterations."""
+    if iterations < 1:
+        raise ValueError("iterations must be positive")
+    if iterations == 1:
+        return np.array([float(delta_init)])
+    return np.array([delta_init * (1.0 - i / (iterations - 1)) for i in range(iterations)])
+
+
 def inpaint(f_masked: np.ndarray, mask: np.ndarray, spectra: np.ndarray, W: np.ndarray, rms: np.ndarray,
-            delta_init: float, delta_min: float, iterations: int) -> np.ndarray:
+            deltas) -> np.ndarray:
     """Shearlet inpainting by iterative hard thresholding (Section 4.3, Algorithm 3).
 
-    f_inpainted = 0, delta = delta_init; each iteration
+    f_inpainted = 0; for each delta of the schedule (``delta_schedule``: the paper's geometric decay)
       f_res = M (f_masked - f_inpainted)
-      f_inpainted = SH^-1 T_{delta RMS} SH (f_res + f_inpainted)
-      delta = lambda delta,  lambda = (delta_min / delta_init)^(1 / (iterations - 1)).
+      f_inpainted = SH^-1 T_{delta RMS} SH (f_res + f_inpainted).
     """
     M = np.asarray(mask, dtype=np.float64)
     fm = np.asarray(f_masked, dtype=np.float64)
     f = np.zeros_like(fm)
     r = np.asarray(rms, dtype=np.float64)
-    for delta in delta_schedule(delta_init, delta_min, iterations):
+    for delta in np.asarray(deltas, dtype=np.float64):
         f_res = M * (fm - f)
         f = denoise(f_res + f, spectra, W, delta * r)
     return f

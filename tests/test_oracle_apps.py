@@ -117,10 +117,27 @@ def test_delta_schedule():
         A.delta_schedule(1.0, 0.1, 0)
 
 
+def test_delta_schedule_linear():
+    d = A.delta_schedule_linear(9.0, 4)
+    assert np.allclose(d, [9.0, 6.0, 3.0, 0.0], rtol=0, atol=1e-15)
+    assert list(A.delta_schedule_linear(2.0, 1)) == [2.0]
+
+
+def test_inpaint_one_step_is_denoising(sys128):
+    # with f_inpainted = 0 the first iteration thresholds the masked image itself
+    s = sys128
+    f = synth.cartoon(128, 128, seed=61)
+    mask = synth.random_mask(128, 128, 0.5, seed=62)
+    fm = (f * mask).astype(np.float64)
+    y = A.inpaint(fm, mask, s.spectra, s.W, s.rms, [40.0])
+    want = A.denoise(fm, s.spectra, s.W, 40.0 * s.rms)
+    assert np.array_equal(y, want)
+
+
 def test_inpaint_full_mask_returns_image(sys128):
     s = sys128
     f = synth.cartoon(128, 128, seed=41)
-    y = A.inpaint(f, np.ones_like(f), s.spectra, s.W, s.rms, 1e-9, 1e-12, 3)
+    y = A.inpaint(f, np.ones_like(f), s.spectra, s.W, s.rms, A.delta_schedule(1e-9, 1e-12, 3))
     assert np.linalg.norm(y - f) <= 1e-10 * np.linalg.norm(f)
 
 
@@ -133,7 +150,11 @@ def test_inpaint_recovers_missing_pixels(sys128):
     # iterations remove the mask's pixel-scale pattern
     d0 = float(np.max(np.abs(OT.forward_plain(fm.astype(np.float64), s.spectra)) / s.rms[:, None, None]))
     assert 200.0 < d0 < 1000.0
-    y = A.inpaint(fm, mask, s.spectra, s.W, s.rms, d0, 1.0, 25)
+    y = A.inpaint(fm, mask, s.spectra, s.W, s.rms, A.delta_schedule(d0, 1.0, 25))
     # the known pixels are matched closely and the masked ones far better than by zeros
     assert A.psnr(f, y) > A.psnr(f, fm) + 15.0
     assert A.psnr(f * mask, y * mask) > 40.0
+    # a linear decay to zero ends with an unthresholded step: the known pixels are reproduced
+    y2 = A.inpaint(fm, mask, s.spectra, s.W, s.rms, A.delta_schedule_linear(d0, 25))
+    assert A.psnr(f, y2) > A.psnr(f, fm) + 15.0
+    assert np.max(np.abs((y2 - f) * mask)) <= 1e-9 * np.max(np.abs(f))
