@@ -138,6 +138,24 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
 int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
                   void* hip_stream);
 
+/* Shearlet inpainting by iterative hard thresholding (Section 4.3, Algorithm 3):
+ *   f = 0; for i < iterations:
+ *     f = SH^-1 T_i SH ( mask (f_masked - f) + f ),
+ * where T_i keeps |c| >= thresholds[i][b][k] (as shear_denoise). The caller
+ * chooses the schedule (Algorithm 3 decays a scalar delta geometrically and
+ * weights it per filter: thresholds[i][b][k] = delta_i * RMS_k).
+ * f_masked, mask, f: batch*rows*cols float32 (device); f receives the result
+ * and must not overlap f_masked or mask. thresholds: iterations*batch*K
+ * float32 (device). The iteration sequence is captured once into a HIP graph
+ * (kept by the system, re-captured when the pointers, batch, iterations or
+ * workspace change) and replayed on hip_stream; with per-launch timing on
+ * (shear_profile_enable) the launches are issued directly instead. The
+ * combination mask (f_masked - f) + f is formed inside the row-FFT kernel.
+ * Runs the separate-launch kernels whatever shear_set_path selected.
+ * Asynchronous. */
+int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, float* f, int batch,
+                  const float* thresholds, int iterations, void* hip_stream);
+
 /* Launch kinds reported by shear_profile_read (one kernel symbol each). */
 #define SHEAR_KERNEL_ROWS_R2C_IMAGES 0 /* forward: row FFT of the images              */
 #define SHEAR_KERNEL_COLS_FWD 1        /* forward: column FFT, x conj filter, IFFT (K-expanding) */
@@ -188,6 +206,21 @@ int shear_profile_read(shear_system* s, int* launches, double* total_ms);
  * exchange slots per image. 0 keeps the current value. SHEAR_E_SIZE if the
  * path does not support the system's size. */
 int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_block);
+
+/* Column-pass schedule of the separate-launch kernels: pw_fwd / pw_inv
+ * columns per block (16 or 8; 16 needs cols >= 32; 0 keeps the current value)
+ * in the forward and in the inverse/adjoint column passes. Results do not
+ * depend on it (every column is transformed by the same operations); speed
+ * does. SHEAR_E_INVALID for other values. */
+int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv);
+
+/* Autotuner: times the column passes of both directions for every compiled
+ * panel width on the system's workspace at this batch size (clearing the
+ * workspace first), keeps the fastest (shear_set_schedule) and reports it
+ * through pw_fwd / pw_inv (either may be NULL). Synchronous: waits for the
+ * device, allocates the workspace for batch if needed, uses the null stream.
+ * Drops any captured inpainting graph. */
+int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv);
 
 /* Waits for hip_stream, then reports SHEAR_E_HIP if the last fused launch of
  * the system gave up on a dependency wait (its output is then invalid). The

@@ -15,6 +15,7 @@ from ._binding import (
 )
 
 from .autograd import ShearletLayer, ShearletTransform
+from .batched import UnevenInpainter
 
 __all__ = ["EXPORTED", "LIB_PATH", "ShearError", "ShearletLayer", "ShearletSystem", "ShearletTransform",
-           "design_spectra", "load_library"]
+           "UnevenInpainter", "design_spectra", "load_library"]

@@ -36,9 +36,12 @@ EXPORTED = (
     "shear_inverse",
     "shear_adjoint",
     "shear_denoise",
+    "shear_inpaint",
     "shear_profile_enable",
     "shear_profile_read",
     "shear_set_path",
+    "shear_set_schedule",
+    "shear_autotune",
     "shear_check",
     "shear_destroy_system",
     "shear_strerror",
@@ -95,10 +98,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in ("shear_forward", "shear_inverse", "shear_adjoint"):
         getattr(lib, name).argtypes = [P, P, P, I, P]
     lib.shear_denoise.argtypes = [P, P, P, I, P, P, P]
+    lib.shear_inpaint.argtypes = [P, P, P, P, I, P, I, P]
     for name in EXPORTED:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
     lib.shear_set_path.argtypes = [P, I, I, I]
+    lib.shear_set_schedule.argtypes = [P, I, I]
+    lib.shear_autotune.argtypes = [P, I, pI, pI]
     lib.shear_check.argtypes = [P, P]
     lib.shear_profile_enable.argtypes = [P, I]
     lib.shear_profile_read.argtypes = [P, pI, pD]
@@ -315,6 +321,33 @@ class ShearletSystem:
             return out, cnt.to(torch.int64)
         return out
 
+    # ------------------------------------------------------------ inpainting
+    def inpaint_thresholds(self, deltas, batch: int) -> np.ndarray:
+        """Algorithm 3's per-filter thresholds: thresholds[i][b][k] = deltas[i] * RMS_k. float32 (I, B, K)."""
+        d = np.asarray(deltas, dtype=np.float64).reshape(-1, 1, 1)
+        return np.ascontiguousarray(np.broadcast_to(d * self.rms.reshape(1, 1, -1), (d.shape[0], batch, self.K)),
+                                    dtype=np.float32)
+
+    def inpaint(self, f_masked, mask, thresholds, out=None, stream=None):
+        """shear_inpaint: Algorithm 3 on a batch (B, rows, cols); thresholds (iterations, B, K) float32."""
+        import torch
+
+        B = f_masked.shape[0]
+        self._check_tensor(f_masked, (B, self.rows, self.cols), "f_masked")
+        self._check_tensor(mask, (B, self.rows, self.cols), "mask")
+        thr = torch.as_tensor(thresholds, dtype=torch.float32, device=f_masked.device).contiguous()
+        if thr.dim() != 3 or thr.shape[1:] != (B, self.K):
+            raise ValueError(f"thresholds must be (iterations, {B}, {self.K}), got {tuple(thr.shape)}")
+        if out is None:
+            out = torch.empty((B, self.rows, self.cols), dtype=torch.float32, device=f_masked.device)
+        self._check_tensor(out, (B, self.rows, self.cols), "out")
+        _check(self._lib.shear_inpaint(self._h, ctypes.c_void_p(f_masked.data_ptr()), ctypes.c_void_p(mask.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), B, ctypes.c_void_p(thr.data_ptr()),
+                                       int(thr.shape[0]), _stream_ptr(stream)), "shear_inpaint")
+        # the graph reads the thresholds when it runs: keep them alive with the output
+        self._keep = thr
+        return out
+
     # ------------------------------------------------------------ execution path
     PATHS = {"pipeline": 0, "separate": 1, "persistent": 2}
 
@@ -322,6 +355,17 @@ class ShearletSystem:
         """Execution path: "separate" (default), "pipeline" or "persistent" (shear_set_path)."""
         _check(self._lib.shear_set_path(self._h, self.PATHS[path], int(chunk_images), int(filters_per_block)),
                "shear_set_path")
+
+    def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0) -> None:
+        """Columns per block of the forward and inverse column passes (shear_set_schedule)."""
+        _check(self._lib.shear_set_schedule(self._h, int(pw_fwd), int(pw_inv)), "shear_set_schedule")
+
+    def autotune(self, batch: int):
+        """Times the compiled column-pass schedules at this batch size and keeps the fastest
+        (shear_autotune); returns (pw_fwd, pw_inv)."""
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(self._lib.shear_autotune(self._h, int(batch), ctypes.byref(a), ctypes.byref(b)), "shear_autotune")
+        return a.value, b.value
 
     def check(self, stream=None) -> None:
         """Waits for the stream and raises if the last fused launch gave up on a dependency (shear_check)."""

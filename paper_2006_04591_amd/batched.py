@@ -1,0 +1,95 @@
+"""Batched inpainting of images of uneven sizes (Section 4.3, Algorithm 3).
+
+Images are grouped by size; each size has its own shearlet system, and each
+group runs as one shear_inpaint call (its whole iteration sequence captured
+as one HIP graph by the library) on a stream of its own, so the groups
+overlap on the GPU. Everything here is host-side grouping and marshalling.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from ._binding import ShearletSystem
+
+__all__ = ["UnevenInpainter", "default_scales"]
+
+
+def default_scales(rows: int, cols: int) -> int:
+    """Scales per size: 3 (33 filters) up to 256 pixels on the short side, else 4 (49 filters)."""
+    return 3 if min(rows, cols) <= 256 else 4
+
+
+class UnevenInpainter:
+    """Holds one system per image size, built on first use; each size's column-pass schedule is
+    autotuned (shear_autotune) for the batch it first runs with."""
+
+    def __init__(self, scales=default_scales, autotune: bool = True):
+        self._scales = scales
+        self._autotune = autotune
+        self._systems: Dict[Tuple[int, int], ShearletSystem] = {}
+        self._streams: Dict[Tuple[int, int], torch.cuda.Stream] = {}
+        self._tuned: Dict[Tuple[int, int], int] = {}
+        self.schedules: Dict[Tuple[int, int], Tuple[int, int]] = {}
+
+    def system(self, rows: int, cols: int) -> ShearletSystem:
+        key = (rows, cols)
+        if key not in self._systems:
+            self._systems[key] = ShearletSystem.build(rows, cols, self._scales(rows, cols))
+        return self._systems[key]
+
+    def run(self, f_masked: Sequence[torch.Tensor], masks: Sequence[torch.Tensor], schedules: Sequence,
+            out: Optional[List[torch.Tensor]] = None) -> List[torch.Tensor]:
+        """Inpaints image i (2-D float32 CUDA tensor) with mask i. schedules[i] is (iterations,) scalars
+        delta (thresholds delta * RMS_k, Algorithm 3) or (iterations, K) per-filter thresholds; every image
+        needs the same number of iterations within its size group. Returns the inpainted images."""
+        n = len(f_masked)
+        if len(masks) != n or len(schedules) != n:
+            raise ValueError("f_masked, masks and schedules must have the same length")
+        groups: Dict[Tuple[int, int], List[int]] = {}
+        for i, t in enumerate(f_masked):
+            if t.dim() != 2:
+                raise ValueError("images must be 2-D")
+            groups.setdefault((int(t.shape[0]), int(t.shape[1])), []).append(i)
+        result: List[Optional[torch.Tensor]] = [None] * n
+        cur = torch.cuda.current_stream()
+        pending = []
+        for key, ids in groups.items():
+            s = self.system(*key)
+            if self._autotune and self._tuned.get(key) != len(ids):
+                # the column-pass schedule of this size at this group's batch (synchronous)
+                self.schedules[key] = s.autotune(len(ids))
+                self._tuned[key] = len(ids)
+            st = self._streams.setdefault(key, torch.cuda.Stream())
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                fm = torch.stack([f_masked[i] for i in ids]).contiguous()
+                mk = torch.stack([masks[i] for i in ids]).contiguous()
+                thr = []
+                for i in ids:
+                    sch = np.asarray(schedules[i], dtype=np.float64)
+                    if sch.ndim == 1:
+                        sch = sch[:, None] * s.rms[None, :]
+                    if sch.ndim != 2 or sch.shape[1] != s.K:
+                        raise ValueError(f"schedule of image {i} must be (iterations,) or (iterations, {s.K})")
+                    thr.append(sch)
+                its = {t.shape[0] for t in thr}
+                if len(its) != 1:
+                    raise ValueError(f"images of size {key} need the same number of iterations")
+                thr_t = torch.from_numpy(np.ascontiguousarray(np.stack(thr, axis=1), dtype=np.float32)).to(fm.device)
+                y = s.inpaint(fm, mk, thr_t, stream=st)
+                for j, i in enumerate(ids):
+                    result[i] = y[j]
+                for t in (fm, mk, thr_t, y):
+                    t.record_stream(st)
+            pending.append(st)
+        for st in pending:
+            cur.wait_stream(st)
+        return result  # type: ignore[return-value]
+
+    def close(self) -> None:
+        for s in self._systems.values():
+            s.close()
+        self._systems.clear()

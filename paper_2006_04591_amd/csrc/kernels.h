@@ -15,6 +15,8 @@ struct DevPlan {
     const float2* twN = nullptr;  // exp(-2 pi i m / N), m < N
     const float2* twL = nullptr;  // exp(-2 pi i m / L), m < L
     const float2* twM = nullptr;  // exp(-2 pi i m / M), m < M
+    int pw_fwd = 16;          // columns per block of the column passes (16 or 8; 8 when L < 16)
+    int pw_inv = 16;
 };
 
 // coeff_planes selects a separate kernel symbol for coefficient planes (same code).
@@ -28,6 +30,10 @@ hipError_t launch_rows_r2c(const DevPlan& d, const float* in, float2* out, int p
 // out = scale * (unnormalised length-M inverse DFT of the Hermitian rows).
 hipError_t launch_rows_c2r(const DevPlan& d, const float2* in, float* out, int planes, float scale, bool coeff_planes,
                            hipStream_t st);
+// Row stage of an inpainting iteration: rows of u = mask (fm - f) + f (planes x N x M each) -> packed
+// column-major spectra, as launch_rows_r2c.
+hipError_t launch_rows_r2c_mix(const DevPlan& d, const float* fm, const float* mask, const float* f, float2* out,
+                               int planes, hipStream_t st);
 // Coefficient row stages with a hard threshold between them, in place on
 // nplanes packed planes; thr[p] and kept[p] (kept may be null) per plane.
 hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,

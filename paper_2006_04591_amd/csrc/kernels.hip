@@ -280,17 +280,17 @@ struct RowPitch {
     static constexpr int value = L + L / P + 1;
 };
 
-template <int M, int P, int ROWS, bool XS = true>
-__device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane, float2* __restrict__ out_plane, int N,
-                                             int row0, float2* lds, const float2* __restrict__ twL,
-                                             const float2* __restrict__ twM, const int tid) {
+// load(row, i) returns samples 2i and 2i+1 of a row of the plane
+template <int M, int P, int ROWS, bool XS, typename Load>
+__device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __restrict__ out_plane, int N, int row0,
+                                                float2* lds, const float2* __restrict__ twL,
+                                                const float2* __restrict__ twM, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
     const int t = tid % T, r = tid / T;
     float2* s = lds + r * PITCH;
-    const float2* src = reinterpret_cast<const float2*>(in_plane + (size_t)(row0 + r) * M);
     float2 v[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) v[q] = ld_stream(src + t + T * q);
+    for (int q = 0; q < P; ++q) v[q] = load(row0 + r, t + T * q);
     fft<L, P, false>(v, s, t, twL);
 #pragma unroll
     for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
@@ -314,6 +314,16 @@ __device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane,
         }
         st_x<XS>(dst + (size_t)k * N, X);
     }
+}
+
+template <int M, int P, int ROWS, bool XS = true>
+__device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane, float2* __restrict__ out_plane, int N,
+                                             int row0, float2* lds, const float2* __restrict__ twL,
+                                             const float2* __restrict__ twM, const int tid) {
+    const float2* src = reinterpret_cast<const float2*>(in_plane);
+    row_r2c_tile_ld<M, P, ROWS, XS>(
+        [src](int row, int i) { return ld_stream(src + (size_t)row * (M / 2) + i); }, out_plane, N, row0, lds, twL,
+        twM, tid);
 }
 
 // packed column-major spectra -> real rows, out = scale * unnormalised inverse
@@ -417,10 +427,24 @@ __device__ __forceinline__ void col_fwd_emit(const float2 (&xh)[P], const void* 
     for (int q = 0; q < P; ++q) st_x<XS>(o + t + T * q, y[q]);
 }
 
+// The mirrored-term accumulator g of packed column 0 lives in the panel's
+// mirror buffer (N float2 of LDS after the FFT scratches), written only by the
+// threads of column 0, each on its own entries: it costs no registers.
+template <int N, int P, int PW>
+__device__ __forceinline__ void col_inv_begin(int col0, float2* lds, const int tid) {
+    constexpr int T = N / P;
+    const int t = tid % T, c = tid / T;
+    float2* smir = lds + PW * ColScratch<N, P>::value;
+    if (col0 + c == 0) {
+#pragma unroll
+        for (int q = 0; q < P; ++q) smir[t + T * q] = make_float2(0.0f, 0.0f);
+    }
+}
+
 // acc += filter_k (.) colFFT(u panel); packed column 0 also accumulates g for the mirrored term.
 template <int N, int P, int PW, bool REAL, bool XS = true>
 __device__ __forceinline__ void col_inv_accum(const float2* __restrict__ u_plane, const void* __restrict__ filt, int k,
-                                              int L, int col0, float2 (&acc)[P], float2 (&g)[P], float2* lds,
+                                              int L, int col0, float2 (&acc)[P], float2* lds,
                                               const float2* __restrict__ twN, const int tid) {
     constexpr int T = N / P;
     const int t = tid % T, c = tid / T;
@@ -436,27 +460,23 @@ __device__ __forceinline__ void col_inv_accum(const float2* __restrict__ u_plane
 #pragma unroll
     for (int q = 0; q < P; ++q) acc[q] = cadd(acc[q], fmul<REAL>(filt, fbase + t + T * q, x[q]));
     if (col == 0) {
+        float2* g = lds + PW * ColScratch<N, P>::value;
         const size_t gbase = (size_t)k * fstride + (size_t)L * N;
 #pragma unroll
-        for (int q = 0; q < P; ++q) g[q] = cadd(g[q], fmul<REAL>(filt, gbase + t + T * q, x[q]));
+        for (int q = 0; q < P; ++q) g[t + T * q] = cadd(g[t + T * q], fmul<REAL>(filt, gbase + t + T * q, x[q]));
     }
 }
 
-// v panel = colIFFT(acc + [column 0: conj g(-m)])
+// v panel = colIFFT(acc + [column 0: conj g(-m)]), g in the mirror buffer
 template <int N, int P, int PW>
-__device__ __forceinline__ void col_inv_finish(float2 (&acc)[P], const float2 (&g)[P], int col0, float2* __restrict__ v_img,
-                                               float2* lds, const float2* __restrict__ twN, const int tid) {
+__device__ __forceinline__ void col_inv_finish(float2 (&acc)[P], int col0, float2* __restrict__ v_img, float2* lds,
+                                               const float2* __restrict__ twN, const int tid) {
     constexpr int T = N / P;
     const int t = tid % T, c = tid / T;
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
-    float2* smir = lds + PW * ColScratch<N, P>::value;
-    __syncthreads();  // the mirror buffer may still be read by a previous user
-    if (col == 0) {
-#pragma unroll
-        for (int q = 0; q < P; ++q) smir[t + T * q] = g[q];
-    }
-    __syncthreads();
+    const float2* smir = lds + PW * ColScratch<N, P>::value;
+    __syncthreads();  // every thread of column 0 has finished its entries of g
     if (col == 0) {
 #pragma unroll
         for (int q = 0; q < P; ++q) {
@@ -484,6 +504,33 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(con
     const int plane = blockIdx.x / nrb;
     const int row0 = (blockIdx.x % nrb) * RB;
     row_r2c_tile<M, Pts<L>::value, RB>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM, (int)threadIdx.x);
+}
+
+// Row stage of one inpainting iteration (Algorithm 3): the rows of
+// u = mask (f_masked - f) + f, formed while loading, -> packed spectra.
+template <int M>
+__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c_mix(const float* __restrict__ fm,
+                                                                                const float* __restrict__ mask,
+                                                                                const float* __restrict__ f,
+                                                                                float2* __restrict__ out, int N,
+                                                                                const float2* __restrict__ twL,
+                                                                                const float2* __restrict__ twM) {
+    constexpr int L = M / 2;
+    extern __shared__ float2 lds[];
+    const int nrb = N / RB;
+    const int plane = blockIdx.x / nrb;
+    const int row0 = (blockIdx.x % nrb) * RB;
+    const size_t off = (size_t)plane * N * L;  // float2 units
+    const float2* a = reinterpret_cast<const float2*>(fm) + off;
+    const float2* m = reinterpret_cast<const float2*>(mask) + off;
+    const float2* g = reinterpret_cast<const float2*>(f) + off;
+    row_r2c_tile_ld<M, Pts<L>::value, RB, true>(
+        [a, m, g](int row, int i) {
+            const size_t j = (size_t)row * L + i;
+            const float2 av = ld_stream(a + j), mv = ld_stream(m + j), gv = g[j];
+            return make_float2(mv.x * (av.x - gv.x) + gv.x, mv.y * (av.y - gv.y) + gv.y);
+        },
+        out + (size_t)plane * L * N, N, row0, lds, twL, twM, (int)threadIdx.x);
 }
 
 template <int M, int TAG>
@@ -632,12 +679,14 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const flo
     constexpr int P = ColCfg<N, PW>::P;
     extern __shared__ float2 lds[];
     const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
-    float2 acc[P], g[P];
+    const int tid = (int)threadIdx.x;
+    float2 acc[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) acc[q] = g[q] = make_float2(0.0f, 0.0f);
+    for (int q = 0; q < P; ++q) acc[q] = make_float2(0.0f, 0.0f);
+    col_inv_begin<N, P, PW>(pan * PW, lds, tid);
     for (int k = 0; k < K; ++k)
-        col_inv_accum<N, P, PW, REAL>(U + ((size_t)b * K + k) * L * N, filt, k, L, pan * PW, acc, g, lds, twN, (int)threadIdx.x);
-    col_inv_finish<N, P, PW>(acc, g, pan * PW, V + (size_t)b * L * N, lds, twN, (int)threadIdx.x);
+        col_inv_accum<N, P, PW, REAL>(U + ((size_t)b * K + k) * L * N, filt, k, L, pan * PW, acc, lds, twN, tid);
+    col_inv_finish<N, P, PW>(acc, pan * PW, V + (size_t)b * L * N, lds, twN, tid);
 }
 
 // ---------------------------------------------------------------- XCD-local persistent kernels
@@ -820,19 +869,20 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS), 4) void k_fu
                     block_signal(&qdone[2 * sl]);
                 }
             } else {
-                float2 acc[PC], gg[PC];
+                float2 acc[PC];
 #pragma unroll
-                for (int qq = 0; qq < PC; ++qq) acc[qq] = gg[qq] = make_float2(0.0f, 0.0f);
+                for (int qq = 0; qq < PC; ++qq) acc[qq] = make_float2(0.0f, 0.0f);
+                col_inv_begin<N, PC, PW>(p * PW, lds, tid);
                 for (int k = 0; k < g.K; ++k) {
                     const int s = k % g.S, sl = i * g.S + s;
                     const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
                     // all row tasks of the plane must have written the slot
                     if (!block_wait(&qdone[2 * sl + 1], (gen + 1) * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
-                    col_inv_accum<N, PC, PW, REAL, false>(qslots + (size_t)sl * plane, bf.filt, k, L, p * PW, acc, gg,
-                                                          lds, bf.twN, tid);
+                    col_inv_accum<N, PC, PW, REAL, false>(qslots + (size_t)sl * plane, bf.filt, k, L, p * PW, acc, lds,
+                                                          bf.twN, tid);
                     block_signal(&qdone[2 * sl]);
                 }
-                col_inv_finish<N, PC, PW>(acc, gg, p * PW, bf.V + (size_t)b * plane, lds, bf.twN, tid);
+                col_inv_finish<N, PC, PW>(acc, p * PW, bf.V + (size_t)b * plane, lds, bf.twN, tid);
             }
         } else {
             // ---------------- row task: tile r of plane (i, k)
@@ -911,12 +961,13 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
         const int p = (task / a.kg) % a.npan;
         const int i = task / (a.kg * a.npan);
         const int b = a.col_b0 + i;
-        float2 acc[PC], gg[PC];
+        float2 acc[PC];
 #pragma unroll
-        for (int q = 0; q < PC; ++q) acc[q] = gg[q] = make_float2(0.0f, 0.0f);
+        for (int q = 0; q < PC; ++q) acc[q] = make_float2(0.0f, 0.0f);
+        col_inv_begin<N, PC, PW>(p * PW, lds, (int)threadIdx.x);
         const int k1 = min(a.K, (g + 1) * a.kper);
         for (int k = g * a.kper; k < k1; ++k)
-            col_inv_accum<N, PC, PW, REAL>(a.bufC + ((size_t)i * a.K + k) * plane, a.filt, k, L, p * PW, acc, gg, lds,
+            col_inv_accum<N, PC, PW, REAL>(a.bufC + ((size_t)i * a.K + k) * plane, a.filt, k, L, p * PW, acc, lds,
                                            a.twN, (int)threadIdx.x);
         // partial spectrum of filter group g (and, for packed column 0, its mirrored-term partial)
         const int t = threadIdx.x % TC, c = threadIdx.x / TC;
@@ -925,9 +976,11 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
 #pragma unroll
         for (int q = 0; q < PC; ++q) o[t + TC * q] = acc[q];
         if (col == 0) {
+            // each thread of column 0 reads back the entries of g it accumulated
+            const float2* sg = lds + PW * ColScratch<N, PC>::value;
             float2* og = a.part0 + ((size_t)b * a.kg + g) * N;
 #pragma unroll
-            for (int q = 0; q < PC; ++q) og[t + TC * q] = gg[q];
+            for (int q = 0; q < PC; ++q) og[t + TC * q] = sg[t + TC * q];
         }
         return;
     }
@@ -963,7 +1016,12 @@ __global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_
             for (int q = 0; q < PC; ++q) gg[q] = cadd(gg[q], sg[t + TC * q]);
         }
     }
-    col_inv_finish<N, PC, PW>(acc, gg, p * PW, a.V + (size_t)b * plane, lds, a.twN, (int)threadIdx.x);
+    if (col == 0) {
+        float2* smir = lds + PW * ColScratch<N, PC>::value;
+#pragma unroll
+        for (int q = 0; q < PC; ++q) smir[t + TC * q] = gg[q];
+    }
+    col_inv_finish<N, PC, PW>(acc, p * PW, a.V + (size_t)b * plane, lds, a.twN, (int)threadIdx.x);
 }
 
 __global__ void k_zero_u32(unsigned* p, int n) {
@@ -998,6 +1056,19 @@ hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes
     const size_t blocks = (size_t)planes * (d.N / RB);
     hipLaunchKernelGGL((k_rows_c2r<M, TAG>), dim3((unsigned)blocks), dim3(RB * T), lds, st, in, out, d.N, d.twL,
                        d.twM, scale);
+    return hipGetLastError();
+}
+
+template <int M>
+hipError_t rows_r2c_mix_t(const DevPlan& d, const float* fm, const float* mask, const float* f, float2* out,
+                          int planes, hipStream_t st) {
+    constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
+    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
+    hipError_t e = set_lds(k_rows_r2c_mix<M>, lds);
+    if (e != hipSuccess) return e;
+    const size_t blocks = (size_t)planes * (d.N / RB);
+    hipLaunchKernelGGL((k_rows_r2c_mix<M>), dim3((unsigned)blocks), dim3(RB * T), lds, st, fm, mask, f, out, d.N,
+                       d.twL, d.twM);
     return hipGetLastError();
 }
 
@@ -1095,6 +1166,20 @@ hipError_t launch_rows_c2r(const DevPlan& d, const float2* in, float* out, int p
     return coeff_planes ? rows_c2r_sw<1>(d, in, out, planes, scale, st) : rows_c2r_sw<0>(d, in, out, planes, scale, st);
 }
 
+hipError_t launch_rows_r2c_mix(const DevPlan& d, const float* fm, const float* mask, const float* f, float2* out,
+                               int planes, hipStream_t st) {
+    switch (d.M) {
+        case 16: return rows_r2c_mix_t<16>(d, fm, mask, f, out, planes, st);
+        case 32: return rows_r2c_mix_t<32>(d, fm, mask, f, out, planes, st);
+        case 64: return rows_r2c_mix_t<64>(d, fm, mask, f, out, planes, st);
+        case 128: return rows_r2c_mix_t<128>(d, fm, mask, f, out, planes, st);
+        case 256: return rows_r2c_mix_t<256>(d, fm, mask, f, out, planes, st);
+        case 512: return rows_r2c_mix_t<512>(d, fm, mask, f, out, planes, st);
+        case 1024: return rows_r2c_mix_t<1024>(d, fm, mask, f, out, planes, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
                               hipStream_t st) {
     switch (d.M) {
@@ -1109,8 +1194,8 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
     return hipErrorInvalidValue;
 }
 
-#define SHEAR_COLS_SWITCH(FN, ...)                                                 \
-    if (d.L >= 16) {                                                               \
+#define SHEAR_COLS_SWITCH(PWSEL, FN, ...)                                          \
+    if (d.L >= 16 && (PWSEL) == 16) {                                              \
         switch (d.N) {                                                             \
             case 16: return FN<16, 16>(__VA_ARGS__);                               \
             case 32: return FN<32, 16>(__VA_ARGS__);                               \
@@ -1120,7 +1205,7 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
             case 512: return FN<512, 16>(__VA_ARGS__);                             \
             case 1024: return FN<1024, 16>(__VA_ARGS__);                           \
         }                                                                          \
-    } else if (d.L == 8) {                                                         \
+    } else if (d.L >= 8) {                                                         \
         switch (d.N) {                                                             \
             case 16: return FN<16, 8>(__VA_ARGS__);                                \
             case 32: return FN<32, 8>(__VA_ARGS__);                                \
@@ -1135,11 +1220,11 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
 
 hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
                            hipStream_t st) {
-    SHEAR_COLS_SWITCH(cols_fwd_t, d, A, T, nimg, filt, scale, st)
+    SHEAR_COLS_SWITCH(d.pw_fwd, cols_fwd_t, d, A, T, nimg, filt, scale, st)
 }
 
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, hipStream_t st) {
-    SHEAR_COLS_SWITCH(cols_inv_t, d, U, V, nimg, filt, st)
+    SHEAR_COLS_SWITCH(d.pw_inv, cols_inv_t, d, U, V, nimg, filt, st)
 }
 
 // ---------------------------------------------------------------- fused dispatch

@@ -57,6 +57,11 @@ struct shear_system {
     shear::FusedInfo finfo[2];    // [0] forward, [1] inverse
     size_t abort_off = 0;         // byte offset of the abort flag in ws (last fused call)
     bool abort_valid = false;
+    // inpainting: the whole iteration sequence of the last call shape, captured as one HIP graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<const void*> graph_key;
 };
 
 namespace {
@@ -233,6 +238,9 @@ void release(shear_system* s) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->dev_block) (void)hipFree(s->dev_block);
     if (s->ws) (void)hipFree(s->ws);
     delete s;
@@ -893,6 +901,165 @@ int shear_denoise(shear_system* s, const float* x, float* y, int batch, const fl
     }
     e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st, [&] { return shear::launch_rows_c2r(d, A, y, batch, 1.0f, false, st); });
     if (e != hipSuccess) return hip_fail(e, "row c2r launch");
+    return SHEAR_OK;
+}
+
+namespace {
+
+// The launches of `iterations` inpainting iterations (Algorithm 3) on stream st.
+hipError_t enqueue_inpaint(shear_system* s, const float* fm, const float* mask, float* f, int batch,
+                           const float* thresholds, int iterations, int chunk, hipStream_t st) {
+    const shear::DevPlan& d = s->plan;
+    const size_t pb = plane_bytes(s) / sizeof(float2);
+    float2* A = (float2*)s->ws;
+    float2* T = A + (size_t)batch * pb;
+    const size_t img = (size_t)d.N * d.M;
+    const float scale = (float)(1.0 / (double)img);
+    // f_inpainted := 0 (a fill kernel, so that the sequence can be captured)
+    hipError_t e = shear::launch_zero_u32(reinterpret_cast<unsigned*>(f), (int)(batch * img), st);
+    if (e != hipSuccess) return e;
+    for (int it = 0; it < iterations; ++it) {
+        e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st,
+                  [&] { return shear::launch_rows_r2c_mix(d, fm, mask, f, A, batch, st); });
+        if (e != hipSuccess) return e;
+        const float* thr = thresholds + (size_t)it * batch * d.K;
+        for (int b0 = 0; b0 < batch; b0 += chunk) {
+            const int nb = std::min(chunk, batch - b0);
+            e = timed(s, SHEAR_KERNEL_COLS_FWD, st,
+                      [&] { return shear::launch_cols_fwd(d, A + (size_t)b0 * pb, T, nb, s->filt_fwd, scale, st); });
+            if (e != hipSuccess) return e;
+            e = timed(s, SHEAR_KERNEL_ROWS_THRESH, st, [&] {
+                return shear::launch_rows_thresh(d, T, nb * d.K, thr + (size_t)b0 * d.K, nullptr, st);
+            });
+            if (e != hipSuccess) return e;
+            e = timed(s, SHEAR_KERNEL_COLS_INV, st,
+                      [&] { return shear::launch_cols_inv(d, T, A + (size_t)b0 * pb, nb, s->filt_inv, st); });
+            if (e != hipSuccess) return e;
+        }
+        e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
+                  [&] { return shear::launch_rows_c2r(d, A, f, batch, 1.0f, false, st); });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+void drop_graph(shear_system* s) {
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->gexec = nullptr;
+    s->graph = nullptr;
+    s->graph_key.clear();
+}
+
+}  // namespace
+
+int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, float* f, int batch,
+                  const float* thresholds, int iterations, void* stream) {
+    int rc = check_call(s, f_masked, f, batch);
+    if (rc != SHEAR_OK) return rc;
+    if (!mask || !thresholds) return fail(SHEAR_E_INVALID, "mask or thresholds pointer is NULL");
+    if (iterations < 1) return fail(SHEAR_E_INVALID, "iterations must be positive");
+    int chunk = 0;
+    if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
+    s->abort_valid = false;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (s->prof_on) {
+        // per-launch timing needs the launches themselves
+        e = enqueue_inpaint(s, f_masked, mask, f, batch, thresholds, iterations, chunk, st);
+        return e == hipSuccess ? SHEAR_OK : hip_fail(e, "inpainting launch");
+    }
+    const std::vector<const void*> key = {f_masked, mask, f, thresholds, s->ws, (const void*)(intptr_t)batch,
+                                          (const void*)(intptr_t)iterations, (const void*)(intptr_t)chunk};
+    if (!s->gexec || key != s->graph_key) {
+        drop_graph(s);
+        if (!s->cap_stream && (e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreateWithFlags");
+        if ((e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+            return hip_fail(e, "hipStreamBeginCapture");
+        const hipError_t el = enqueue_inpaint(s, f_masked, mask, f, batch, thresholds, iterations, chunk, s->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(s->cap_stream, &g);
+        if (el != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return hip_fail(el, "inpainting launch under capture");
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        s->graph = g;
+        if ((e = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+            drop_graph(s);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        s->graph_key = key;
+    }
+    if ((e = hipGraphLaunch(s->gexec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SHEAR_OK;
+}
+
+int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    const int L = s->cols / 2;
+    for (int pw : {pw_fwd, pw_inv}) {
+        if (pw != 0 && pw != 8 && pw != 16) return fail(SHEAR_E_INVALID, "panel width must be 0, 8 or 16");
+        if (pw == 16 && L < 16) return fail(SHEAR_E_INVALID, "panel width 16 needs cols >= 32");
+    }
+    if (pw_fwd) s->plan.pw_fwd = pw_fwd;
+    if (pw_inv) s->plan.pw_inv = pw_inv;
+    return SHEAR_OK;
+}
+
+int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv) {
+    int rc = check_call(s, s, s, batch);
+    if (rc != SHEAR_OK) return rc;
+    int chunk = 0;
+    if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
+    drop_graph(s);  // a captured inpainting sequence holds the old schedule
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    // defined contents for the timing runs
+    e = shear::launch_zero_u32((unsigned*)s->ws, (int)std::min<size_t>(s->ws_bytes / 4, (size_t)1 << 30), nullptr);
+    if (e != hipSuccess) return hip_fail(e, "workspace clear");
+    const size_t pb = plane_bytes(s) / sizeof(float2);
+    float2* A = (float2*)s->ws;
+    float2* T = A + (size_t)batch * pb;
+    const float scale = (float)(1.0 / ((double)s->rows * s->cols));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    std::vector<int> cand = {8};
+    if (s->cols / 2 >= 16) cand.insert(cand.begin(), 16);
+    constexpr int kReps = 3;
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+        float best = 0.0f;
+        int pick = cand[0];
+        for (int pw : cand) {
+            shear::DevPlan d = s->plan;
+            (dir == 0 ? d.pw_fwd : d.pw_inv) = pw;
+            auto launch = [&] {
+                return dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
+                                : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, nullptr);
+            };
+            if ((e = launch()) != hipSuccess) break;  // warm-up
+            if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) break;
+            for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch();
+            if (e != hipSuccess) break;
+            if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.0f;
+            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+            if (pw == cand[0] || ms < best) {
+                best = ms;
+                pick = pw;
+            }
+        }
+        if (e == hipSuccess) (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "autotune launch");
+    if (pw_fwd) *pw_fwd = s->plan.pw_fwd;
+    if (pw_inv) *pw_inv = s->plan.pw_inv;
     return SHEAR_OK;
 }
 

@@ -379,3 +379,44 @@ def test_path_profile_kinds(cfg1, gpu):
     assert rec["persistent"]["fused_fwd"][0] == 1 and rec["persistent"]["fused_inv"][0] == 1
     assert rec["pipeline"]["pipe_fwd"][0] == 2 and rec["pipeline"]["pipe_inv"][0] == 2
     assert rec["pipeline"]["pipe_finish"][0] == 1 and rec["pipeline"]["cols_fwd"][0] == 0
+
+
+# ---------------------------------------------------------------- column-pass schedules and the autotuner
+
+
+@pytest.mark.parametrize("N,M,J,B", [(256, 256, 3, 4), (1024, 1024, 4, 2), (512, 128, 2, 3)])
+def test_schedules_agree_and_autotune(gpu, lib, N, M, J, B):
+    """Every column-pass schedule transforms each column with the same operations: the forward is
+    bitwise identical, the inverse agrees to rounding; the autotuner keeps one of them."""
+    from paper_2006_04591_amd import ShearletSystem
+
+    _say(f"case: schedules {N}x{M} J={J} B={B}")
+    with ShearletSystem.build(N, M, J) as s:
+        x = _to(synth.cartoon_batch(B, N, M, config=8, sigma=5.0), gpu)
+        res = {}
+        for pw in (16, 8):
+            s.set_schedule(pw, pw)
+            c = s.forward(x)
+            res[pw] = (c, s.inverse(c))
+        torch.cuda.synchronize()
+        assert torch.equal(res[16][0], res[8][0])
+        assert _rel(res[8][1].cpu().numpy(), res[16][1].cpu().numpy()) <= 1e-6
+        assert _rel(res[16][1].cpu().numpy(), x.cpu().numpy()) <= TOL
+        pf, pi = s.autotune(B)
+        assert pf in (8, 16) and pi in (8, 16)
+        c = s.forward(x)
+        torch.cuda.synchronize()
+        assert torch.equal(c, res[pf][0])
+        with pytest.raises(Exception):
+            s.set_schedule(12, 0)
+
+
+def test_schedule_narrow_columns(gpu, lib):
+    from paper_2006_04591_amd import ShearError, ShearletSystem
+
+    rng = np.random.default_rng(9)
+    S = np.fft.fftshift(np.fft.fft2(rng.standard_normal((2, 32, 16))), axes=(1, 2))
+    with ShearletSystem.from_spectra(S) as s:
+        with pytest.raises(ShearError):
+            s.set_schedule(16, 0)  # 8 packed columns: one panel of 8
+        assert s.autotune(2) == (8, 8)

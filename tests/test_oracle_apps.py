@@ -134,6 +134,16 @@ def test_inpaint_one_step_is_denoising(sys128):
     assert np.array_equal(y, want)
 
 
+def test_inpaint_per_filter_rows_equal_scalar_schedule(sys128):
+    s = sys128
+    f = synth.cartoon(128, 128, seed=71)
+    mask = synth.random_mask(128, 128, 0.5, seed=72)
+    d = A.delta_schedule(300.0, 2.0, 4)
+    y1 = A.inpaint(f * mask, mask, s.spectra, s.W, s.rms, d)
+    y2 = A.inpaint(f * mask, mask, s.spectra, s.W, s.rms, d[:, None] * s.rms[None, :])
+    assert np.array_equal(y1, y2)
+
+
 def test_inpaint_full_mask_returns_image(sys128):
     s = sys128
     f = synth.cartoon(128, 128, seed=41)
