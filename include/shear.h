@@ -156,6 +156,34 @@ int shear_denoise(shear_system* s, const float* x, float* y, int batch, const fl
 int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, float* f, int batch,
                   const float* thresholds, int iterations, void* hip_stream);
 
+/* Learned shrinkage (not in the paper: a small network predicts the
+ * thresholds of Section 4.2's hard thresholding per coefficient). With
+ * z_k = c_k / (sigma_b RMS_k):
+ *   h1 = relu(conv3x3(z; W1) + b1), h2 = relu(conv3x3(h1; W2) + b2),
+ *   tau_k = softplus(conv3x3(h2; W3) + b3_k)  (0 on the low-pass plane, the last),
+ *   shrunk_k = c_k where |z_k| >= tau_k, else 0,
+ * conv3x3 a cross-correlation with circular boundary over 3x3 taps, W1 32xKx3x3,
+ * W2 32x32x3x3, W3 Kx32x3x3 (FP32, natural order [out][in][dy][dx]), biases FP32.
+ * The matrix-core kernels compute with bfloat16 operands (z, weights and the
+ * hidden activations rounded to bfloat16) and FP32 accumulation. K <= 64,
+ * rows % 8 == 0, cols % 32 == 0 (else SHEAR_E_SIZE). */
+
+/* Bytes of the packed (device) parameter block of a K-filter network. */
+int shear_shrink_params_bytes(int K, size_t* bytes);
+
+/* Packs FP32 device parameters into the device block `packed` (bfloat16
+ * weights in the kernels' order, padded); asynchronous on hip_stream. */
+int shear_shrink_pack(shear_system* s, const float* W1, const float* b1, const float* W2, const float* b2,
+                      const float* W3, const float* b3, void* packed, void* hip_stream);
+
+/* coeffs (batch*K*rows*cols float32, device, as shear_forward writes them) ->
+ * shrunk (same shape; must not overlap coeffs) and, if tau is non-NULL, the
+ * thresholds tau (same shape, noise units). sigma: batch float32 (device),
+ * the noise level of each image. The system keeps a workspace of
+ * 64*batch*rows*cols bytes for the hidden activations. Asynchronous. */
+int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, float* tau, int batch, const float* sigma,
+                       const void* packed, void* hip_stream);
+
 /* Launch kinds reported by shear_profile_read (one kernel symbol each). */
 #define SHEAR_KERNEL_ROWS_R2C_IMAGES 0 /* forward: row FFT of the images              */
 #define SHEAR_KERNEL_COLS_FWD 1        /* forward: column FFT, x conj filter, IFFT (K-expanding) */

@@ -10,6 +10,7 @@ from ._binding import (
     LIB_PATH,
     ShearError,
     ShearletSystem,
+    ShrinkNet,
     design_spectra,
     load_library,
 )
@@ -18,4 +19,4 @@ from .autograd import ShearletLayer, ShearletTransform
 from .batched import UnevenInpainter
 
 __all__ = ["EXPORTED", "LIB_PATH", "ShearError", "ShearletLayer", "ShearletSystem", "ShearletTransform",
-           "UnevenInpainter", "design_spectra", "load_library"]
+           "ShrinkNet", "UnevenInpainter", "design_spectra", "load_library"]

@@ -42,6 +42,9 @@ EXPORTED = (
     "shear_set_path",
     "shear_set_schedule",
     "shear_autotune",
+    "shear_shrink_params_bytes",
+    "shear_shrink_pack",
+    "shear_shrink_apply",
     "shear_check",
     "shear_destroy_system",
     "shear_strerror",
@@ -104,6 +107,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
             getattr(lib, name).restype = I
     lib.shear_set_path.argtypes = [P, I, I, I]
     lib.shear_set_schedule.argtypes = [P, I, I]
+    lib.shear_shrink_params_bytes.argtypes = [I, ctypes.POINTER(ctypes.c_size_t)]
+    lib.shear_shrink_pack.argtypes = [P, P, P, P, P, P, P, P, P]
+    lib.shear_shrink_apply.argtypes = [P, P, P, P, I, P, P, P]
     lib.shear_autotune.argtypes = [P, I, pI, pI]
     lib.shear_check.argtypes = [P, P]
     lib.shear_profile_enable.argtypes = [P, I]
@@ -403,3 +409,58 @@ class ShearletSystem:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class ShrinkNet:
+    """Learned shrinkage network of a system (shear_shrink_pack / shear_shrink_apply): FP32 parameters
+    W1 (32, K, 3, 3), b1 (32,), W2 (32, 32, 3, 3), b2 (32,), W3 (K, 32, 3, 3), b3 (K,) as CUDA tensors,
+    and their packed bfloat16 block."""
+
+    NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+
+    def __init__(self, system: ShearletSystem, params: dict, device=None):
+        import torch
+
+        self.system = system
+        self._lib = system._lib
+        dev = device if device is not None else torch.device("cuda")
+        K = system.K
+        shapes = {"W1": (32, K, 3, 3), "b1": (32,), "W2": (32, 32, 3, 3), "b2": (32,), "W3": (K, 32, 3, 3), "b3": (K,)}
+        self.params = {}
+        for n in self.NAMES:
+            t = torch.as_tensor(params[n], dtype=torch.float32, device=dev).contiguous()
+            if tuple(t.shape) != shapes[n]:
+                raise ValueError(f"{n} has shape {tuple(t.shape)}, expected {shapes[n]}")
+            self.params[n] = t
+        nb = ctypes.c_size_t()
+        _check(self._lib.shear_shrink_params_bytes(K, ctypes.byref(nb)), "shear_shrink_params_bytes")
+        self.packed = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+        self.pack()
+
+    def pack(self, stream=None) -> None:
+        """Re-packs the FP32 parameters (after they change) into the bfloat16 block."""
+        p = [ctypes.c_void_p(self.params[n].data_ptr()) for n in self.NAMES]
+        _check(self._lib.shear_shrink_pack(self.system._h, *p, ctypes.c_void_p(self.packed.data_ptr()),
+                                           _stream_ptr(stream)), "shear_shrink_pack")
+
+    def apply(self, coeffs, sigma, out=None, tau: bool = False, stream=None):
+        """Shrunk coefficients (and the thresholds tau, noise units, when tau is True)."""
+        import torch
+
+        s = self.system
+        B = coeffs.shape[0]
+        s._check_tensor(coeffs, (B, s.K, s.rows, s.cols), "coeffs")
+        sig = torch.as_tensor(sigma, dtype=torch.float32, device=coeffs.device)
+        if sig.dim() == 0:
+            sig = sig.expand(B)
+        sig = sig.contiguous()
+        s._check_tensor(sig, (B,), "sigma")
+        if out is None:
+            out = torch.empty_like(coeffs)
+        s._check_tensor(out, (B, s.K, s.rows, s.cols), "out")
+        t = torch.empty_like(coeffs) if tau else None
+        _check(self._lib.shear_shrink_apply(s._h, ctypes.c_void_p(coeffs.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(t.data_ptr()) if tau else None, B,
+                                            ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(self.packed.data_ptr()),
+                                            _stream_ptr(stream)), "shear_shrink_apply")
+        return (out, t) if tau else out

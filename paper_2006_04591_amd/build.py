@@ -11,7 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libshear.so")
-SOURCES = ["builder.cpp", "shear_api.cpp", "kernels.hip"]
+SOURCES = ["builder.cpp", "shear_api.cpp", "kernels.hip", "shrink.hip"]
 
 
 def hipcc() -> str:

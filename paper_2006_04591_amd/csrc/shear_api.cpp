@@ -16,6 +16,7 @@
 #include "builder.h"
 #include "kernels.h"
 #include "shear.h"
+#include "shrink.h"
 
 using shear::cd;
 
@@ -32,6 +33,7 @@ struct shear_system {
     const void* filt_fwd = nullptr;
     const void* filt_inv = nullptr;
     const void* filt_adj = nullptr;
+    const float* rms_dev = nullptr;  // RMS_k as float (learned shrinkage)
     shear::DevPlan plan;
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -62,6 +64,9 @@ struct shear_system {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<const void*> graph_key;
+    // learned shrinkage: scales and hidden activations
+    void* ws2 = nullptr;
+    size_t ws2_bytes = 0;
 };
 
 namespace {
@@ -190,7 +195,9 @@ int finish_system(shear_system* s, std::string& why) {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t b_tw = al(tw.size() * sizeof(float));
     const size_t b_f = al(ffwd.size() * sizeof(float));
-    const size_t total = b_tw + 3 * b_f;
+    std::vector<float> rms32(s->rms.begin(), s->rms.end());
+    const size_t b_r = al((size_t)K * sizeof(float));
+    const size_t total = b_tw + 3 * b_f + b_r;
     hipError_t e = hipMalloc(&s->dev_block, total);
     if (e != hipSuccess) {
         s->dev_block = nullptr;
@@ -202,6 +209,8 @@ int finish_system(shear_system* s, std::string& why) {
         (e = hipMemcpy(base + b_tw, ffwd.data(), ffwd.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(base + b_tw + b_f, finv.data(), finv.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(base + b_tw + 2 * b_f, fadj.data(), fadj.size() * sizeof(float), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(base + b_tw + 3 * b_f, rms32.data(), rms32.size() * sizeof(float), hipMemcpyHostToDevice)) !=
             hipSuccess) {
         why = std::string("hipMemcpy of the filter bank failed: ") + hipGetErrorString(e);
         return SHEAR_E_HIP;
@@ -218,6 +227,7 @@ int finish_system(shear_system* s, std::string& why) {
     s->filt_fwd = base + b_tw;
     s->filt_inv = base + b_tw + b_f;
     s->filt_adj = base + b_tw + 2 * b_f;
+    s->rms_dev = (const float*)(base + b_tw + 3 * b_f);
     s->fused = false;
     if (shear::fused_supported(N, M)) {
         if ((e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess ||
@@ -243,6 +253,7 @@ void release(shear_system* s) {
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
     if (s->dev_block) (void)hipFree(s->dev_block);
     if (s->ws) (void)hipFree(s->ws);
+    if (s->ws2) (void)hipFree(s->ws2);
     delete s;
 }
 
@@ -1060,6 +1071,89 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv) {
     if (e != hipSuccess) return hip_fail(e, "autotune launch");
     if (pw_fwd) *pw_fwd = s->plan.pw_fwd;
     if (pw_inv) *pw_inv = s->plan.pw_inv;
+    return SHEAR_OK;
+}
+
+int shear_shrink_params_bytes(int K, size_t* bytes) {
+    if (!bytes || K < 1 || K > 64) return fail(SHEAR_E_INVALID, "K must be in [1, 64] and bytes non-NULL");
+    *bytes = shear::shrink_layout(K).bytes;
+    return SHEAR_OK;
+}
+
+int shear_shrink_pack(shear_system* s, const float* W1, const float* b1, const float* W2, const float* b2,
+                      const float* W3, const float* b3, void* packed, void* stream) {
+    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    if (!W1 || !b1 || !W2 || !b2 || !W3 || !b3 || !packed) return fail(SHEAR_E_INVALID, "NULL parameter pointer");
+    if (s->K > 64) return fail(SHEAR_E_SIZE, "learned shrinkage supports at most 64 filters");
+    hipError_t e = shear::launch_shrink_pack(s->K, W1, b1, W2, b2, W3, b3, packed, (hipStream_t)stream);
+    return e == hipSuccess ? SHEAR_OK : hip_fail(e, "parameter packing launch");
+}
+
+int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, float* tau, int batch, const float* sigma,
+                       const void* packed, void* stream) {
+    int rc = check_call(s, coeffs, shrunk, batch);
+    if (rc != SHEAR_OK) return rc;
+    if (!sigma || !packed) return fail(SHEAR_E_INVALID, "sigma or parameter pointer is NULL");
+    if (!shear::shrink_supported(s->K, s->rows, s->cols))
+        return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 32 == 0");
+    const int K = s->K, N = s->rows, M = s->cols;
+    const size_t act = (size_t)batch * N * M * 32 * 2;  // one bfloat16 activation tensor
+    const size_t sc = ((size_t)batch * K * sizeof(float) + 255) & ~(size_t)255;
+    const size_t need = sc + 2 * act;
+    if (need > s->ws2_bytes) {
+        if (s->ws2) {
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before workspace growth");
+            (void)hipFree(s->ws2);
+            s->ws2 = nullptr;
+            s->ws2_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&s->ws2, need);
+        if (e != hipSuccess) {
+            s->ws2 = nullptr;
+            return fail(SHEAR_E_NOMEM, std::string("shrinkage workspace hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        s->ws2_bytes = need;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    char* w = (char*)s->ws2;
+    float* scale = (float*)w;
+    void* h1 = w + sc;
+    void* h2 = w + sc + act;
+    const shear::ShrinkLayout L = shear::shrink_layout(K);
+    const char* p = (const char*)packed;
+    hipError_t e = shear::launch_inv_scale(sigma, s->rms_dev, scale, batch, K, st);
+    if (e != hipSuccess) return hip_fail(e, "scale launch");
+    shear::ConvArgs a{};
+    a.N = N;
+    a.M = M;
+    a.scale = scale;
+    a.lowpass = K - 1;
+    // layer 1: coefficients -> h1
+    a.in = coeffs;
+    a.W = (const unsigned short*)(p + L.w1);
+    a.bias = (const float*)(p + L.b1);
+    a.out_bf = h1;
+    a.cin = K;
+    a.cout = 32;
+    if ((e = shear::launch_conv(0, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 1 launch");
+    // layer 2: h1 -> h2
+    a.in = h1;
+    a.W = (const unsigned short*)(p + L.w2);
+    a.bias = (const float*)(p + L.b2);
+    a.out_bf = h2;
+    a.cin = 32;
+    if ((e = shear::launch_conv(1, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 2 launch");
+    // layer 3: h2 -> thresholds -> shrunk coefficients
+    a.in = h2;
+    a.W = (const unsigned short*)(p + L.w3);
+    a.bias = (const float*)(p + L.b3);
+    a.out_bf = nullptr;
+    a.coef = coeffs;
+    a.out_f = shrunk;
+    a.tau = tau;
+    a.cout = K;
+    if ((e = shear::launch_conv(2, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 3 launch");
     return SHEAR_OK;
 }
 

@@ -1,0 +1,46 @@
+// Internal launch interface of the learned-shrinkage kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+namespace shear {
+
+// One 3x3 layer launch. Layer 0 reads FP32 channel-first coefficients (in,
+// scaled by scale[b*cin + c]); layers 1 and 2 read bfloat16 channel-last
+// activations [b][y][x][32]. Layers 0 and 1 write relu(conv + bias) as
+// bfloat16 channel-last activations (out_bf); layer 2 writes the shrunk FP32
+// coefficients out_f (coef kept where |coef * scale| >= softplus(conv + bias),
+// plane `lowpass` kept whole) and, if non-null, the thresholds tau.
+struct ConvArgs {
+    const void* in;
+    const unsigned short* W;  // packed bfloat16 weights [coutp][9][cinp]
+    const float* bias;
+    const float* scale;       // [B][K] 1 / (sigma_b RMS_k)
+    const float* coef;        // layer 2: the coefficients (B x K x N x M)
+    void* out_bf;
+    float* out_f;
+    float* tau;
+    int N, M;
+    int cin, cout;            // real channel counts (K for the coefficient side)
+    int lowpass;
+};
+
+// Byte offsets of the packed parameter block of a K-filter network.
+struct ShrinkLayout {
+    size_t w1, w2, w3, b1, b2, b3, bytes;
+};
+
+int shrink_cinp(int K);   // padded input channels of layer 0 (32 or 64)
+int shrink_coutp(int K);  // padded output channels of layer 2 (multiple of 16)
+bool shrink_supported(int K, int N, int M);
+ShrinkLayout shrink_layout(int K);
+
+// FP32 natural-layout parameters (device) -> packed block (device).
+hipError_t launch_shrink_pack(int K, const float* W1, const float* b1, const float* W2, const float* b2,
+                              const float* W3, const float* b3, void* packed, hipStream_t st);
+hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, int B, int K, hipStream_t st);
+hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st);
+
+}  // namespace shear

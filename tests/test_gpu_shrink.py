@@ -1,0 +1,135 @@
+"""GPU parity of the learned-shrinkage network (matrix-core kernels, bfloat16
+operands, FP32 accumulation) against the FP64 oracle network.
+
+Tolerance. Both sides round the same operands to bfloat16. The oracle's
+values before rounding differ from the GPU's by the FP32 accumulation error
+(about 1e-7 relative), so a value that lands within that distance of a
+bfloat16 rounding boundary can round to the neighbouring bfloat16 (2^-8
+relative) on one side only. Such flips are rare: they change tau by far less
+than 1e-3 in relative L2, the bound used here. The keep/zero decision is
+compared where |z| is not within 1e-3 tau of tau; inside that band either
+decision is valid, and the band holds only a small fraction of the coefficients.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import apps as OA
+from oracle import filters as OF
+from oracle import shrink as OS
+from oracle import transform as OT
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+TAU_TOL = 1e-3
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _to(x, dev):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dev)
+
+
+def _params_dict(p):
+    return {"W1": p.W1, "b1": p.b1, "W2": p.W2, "b2": p.b2, "W3": p.W3, "b3": p.b3}
+
+
+def _check(got_c, got_t, c32, sigma, rms, p):
+    want_c, want_t = OS.shrink(c32.astype(np.float64), sigma, rms, p)
+    assert _rel(got_t, want_t) <= TAU_TOL
+    z = c32.astype(np.float64) / (sigma * rms[:, None, None])
+    clear = np.abs(np.abs(z) - want_t) > 1e-3 * np.maximum(want_t, 1e-3)
+    assert clear.mean() > 0.99
+    assert np.array_equal(got_c[clear], want_c[clear])
+    # inside the band, each output is either the coefficient or zero
+    amb = ~clear
+    assert np.all((got_c[amb] == c32[amb]) | (got_c[amb] == 0.0))
+
+
+def test_shrink_matches_oracle_128(gpu):
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say("case: shrink 128x128 K=17 B=2")
+    ref = OF.build_system(128, 128, 2)
+    sig = np.array([20.0, 35.0])
+    x = np.stack([synth.cartoon(128, 128, seed=9100 + b) + synth.gaussian_noise(128, 128, sig[b], seed=9150 + b)
+                  for b in range(2)])
+    c32 = np.stack([OT.forward_plain(x[b].astype(np.float64), ref.spectra) for b in range(2)]).astype(np.float32)
+    p = OS.init_params(ref.K, seed=5, tau0=3.0)
+    p.W3 *= 10.0  # thresholds that vary clearly across coefficients
+    p = OS.ShrinkParams(p.W1, p.b1, p.W2, p.b2, p.W3, p.b3)
+    with ShearletSystem.build(128, 128, 2) as s:
+        net = ShrinkNet(s, _params_dict(p))
+        out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        torch.cuda.synchronize()
+        for b in range(2):
+            _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], ref.rms, p)
+        assert float(tau[:, :-1].std()) > 0.1  # the network's thresholds do vary
+
+
+def test_untrained_shrink_is_hard_threshold(gpu):
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say("case: untrained shrink = hard threshold 3 sigma RMS")
+    ref = OF.build_system(128, 128, 2)
+    x = synth.cartoon_batch(3, 128, 128, config=9, sigma=25.0)
+    c32 = np.stack([OT.forward_plain(x[b].astype(np.float64), ref.spectra) for b in range(3)]).astype(np.float32)
+    p = OS.init_params(ref.K, seed=6, tau0=3.0)
+    p.W3[:] = 0.0
+    with ShearletSystem.build(128, 128, 2) as s:
+        net = ShrinkNet(s, _params_dict(p))
+        out = net.apply(_to(c32, gpu), 25.0)
+        torch.cuda.synchronize()
+        delta = 3.0 * 25.0 * ref.rms
+        delta[-1] = 0.0
+        for b in range(3):
+            want = OA.hard_threshold(c32[b].astype(np.float64), delta)
+            near = np.abs(np.abs(c32[b]) - delta[:, None, None]) <= 1e-5 * delta[:, None, None]
+            got = out[b].cpu().numpy()
+            assert np.array_equal(got[~near], want[~near])
+
+
+def test_shrink_tile_borders_user_bank(gpu):
+    """A 64x128 user bank (K=5): tiles of 8x32 pixels with wrapped halos on every side."""
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say("case: shrink 64x128 K=5 B=3")
+    rng = np.random.default_rng(12)
+    S = np.fft.fft2(rng.standard_normal((5, 64, 128)))
+    rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+    c32 = (rng.standard_normal((3, 5, 64, 128)) * 30.0 * rms[None, :, None, None]).astype(np.float32)
+    sig = np.array([10.0, 30.0, 50.0])
+    p = OS.init_params(5, seed=7, tau0=2.0)
+    p.W3 *= 10.0
+    p = OS.ShrinkParams(p.W1, p.b1 + 0.1, p.W2, p.b2 - 0.05, p.W3, p.b3)
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        assert np.allclose(s.rms, rms, rtol=1e-12)
+        net = ShrinkNet(s, _params_dict(p))
+        out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        torch.cuda.synchronize()
+        for b in range(3):
+            _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], rms, p)
+
+
+def test_shrink_errors(gpu):
+    from paper_2006_04591_amd import ShearError, ShearletSystem, ShrinkNet
+
+    rng = np.random.default_rng(13)
+    S = np.fft.fftshift(np.fft.fft2(rng.standard_normal((2, 16, 16))), axes=(1, 2))
+    p = OS.init_params(2, seed=1)
+    with ShearletSystem.from_spectra(S) as s:
+        net = ShrinkNet(s, _params_dict(p))
+        with pytest.raises(ShearError) as e:
+            net.apply(_to(np.zeros((1, 2, 16, 16)), gpu), 1.0)  # 16 columns: below one 32-column tile
+        assert e.value.name == "SHEAR_E_SIZE"
+        with pytest.raises(ValueError):
+            ShrinkNet(s, {**_params_dict(p), "W1": np.zeros((32, 3, 3, 3))})
