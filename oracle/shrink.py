@@ -18,6 +18,15 @@ are periodic): out[co](y, x) = sum_{ci, dy, dx} W[co, ci, dy, dx] in[ci](y+dy-1,
 The network computes with bfloat16 operands and FP32 accumulation; the
 oracle rounds the same operands to bfloat16 (z, the weights, h1, h2) and
 accumulates in FP64. Biases, o and tau are not rounded.
+
+Training objective (not in the paper; the workload's): the hard threshold is
+replaced by a smooth gate so that it can be differentiated,
+  g = sigmoid((|z| - tau) / T),   z_hat = z g,
+  L = scale * sum over images, band planes (not the low-pass) and pixels of (z_hat - z_clean)^2,
+z_clean the noise-normalised coefficients of the clean image. ``train_loss``
+returns L and its gradients by the chain rule (rounding points treated as the
+identity, as the kernels do; with ``rounded`` the gradients flowing back are
+rounded to bfloat16 where the kernels store them).
 """
 from __future__ import annotations
 
@@ -31,6 +40,8 @@ __all__ = [
     "init_params",
     "thresholds",
     "shrink",
+    "conv3x3_adjoint",
+    "train_loss",
 ]
 
 
@@ -112,3 +123,62 @@ def shrink(c: np.ndarray, sigma: float, rms: np.ndarray, p: ShrinkParams, lowpas
     tau = thresholds(c, sigma, rms, p, lowpass)
     z = c / (float(sigma) * np.asarray(rms, dtype=np.float64))[:, None, None]
     return np.where(np.abs(z) >= tau, c, 0.0), tau
+
+
+def conv3x3_adjoint(d: np.ndarray, W: np.ndarray) -> np.ndarray:
+    """Adjoint of conv3x3_circular in its input: out[ci](y, x) = sum_{co,dy,dx} W[co, ci, dy, dx] d[co](y-dy+1, x-dx+1)."""
+    d = np.asarray(d, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    out = np.zeros((W.shape[1],) + d.shape[1:])
+    for dy in range(3):
+        for dx in range(3):
+            out += np.einsum("oc,oyx->cyx", W[:, :, dy, dx], np.roll(d, shift=(dy - 1, dx - 1), axis=(1, 2)))
+    return out
+
+
+def _wgrad(d: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """dW[co, ci, dy, dx] = sum_{y,x} d[co](y, x) x[ci](y+dy-1, x+dx-1)."""
+    out = np.zeros((d.shape[0], x.shape[0], 3, 3))
+    for dy in range(3):
+        for dx in range(3):
+            out[:, :, dy, dx] = np.einsum("oyx,cyx->oc", d, np.roll(x, shift=(1 - dy, 1 - dx), axis=(1, 2)))
+    return out
+
+
+def _sigmoid(x):
+    return 0.5 * (1.0 + np.tanh(0.5 * x))
+
+
+def train_loss(c_noisy, c_clean, sigma, rms, p: ShrinkParams, temperature: float, scale: float,
+               rounded: bool = True, lowpass: int | None = None):
+    """(L, grads dict W1, b1, W2, b2, W3, b3) for one image (K, N, M) of noise level sigma."""
+    r = (lambda v: to_bf16(v)) if rounded else (lambda v: v)
+    c_noisy = np.asarray(c_noisy, dtype=np.float64)
+    K = c_noisy.shape[0]
+    lp = K - 1 if lowpass is None else lowpass
+    sc = 1.0 / (float(sigma) * np.asarray(rms, dtype=np.float64))[:, None, None]
+    z = c_noisy * sc
+    zc = np.asarray(c_clean, dtype=np.float64) * sc
+    zb = r(z)
+    a1 = conv3x3_circular(zb, p.W1, p.b1)
+    h1 = r(np.maximum(a1, 0.0))
+    a2 = conv3x3_circular(h1, p.W2, p.b2)
+    h2 = r(np.maximum(a2, 0.0))
+    o = conv3x3_circular(h2, p.W3, p.b3)
+    tau = softplus(o)
+    g = _sigmoid((np.abs(z) - tau) / temperature)
+    res = z * g - zc
+    band = np.ones(K, dtype=bool)
+    band[lp] = False
+    L = float(scale * np.sum(res[band] ** 2))
+    do = 2.0 * scale * res * z * g * (1.0 - g) * (-1.0 / temperature) * _sigmoid(o)
+    do[lp] = 0.0
+    do = r(do)
+    grads = {"W3": _wgrad(do, h2), "b3": do.sum(axis=(1, 2))}
+    dh2 = r(conv3x3_adjoint(do, p.W3) * (h2 > 0))
+    grads["W2"] = _wgrad(dh2, h1)
+    grads["b2"] = dh2.sum(axis=(1, 2))
+    dh1 = r(conv3x3_adjoint(dh2, p.W2) * (h1 > 0))
+    grads["W1"] = _wgrad(dh1, zb)
+    grads["b1"] = dh1.sum(axis=(1, 2))
+    return L, grads

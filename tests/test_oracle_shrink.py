@@ -83,3 +83,44 @@ def test_init_params_output_bias():
     assert np.allclose(S.softplus(p.b3), 2.5, rtol=1e-6)
     assert p.W1.shape == (32, 7, 3, 3) and p.W3.shape == (7, 32, 3, 3)
     assert np.array_equal(S.to_bf16(p.W2), p.W2)
+
+
+def test_conv_adjoint_identity():
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((3, 8, 16))
+    d = rng.standard_normal((4, 8, 16))
+    W = rng.standard_normal((4, 3, 3, 3))
+    lhs = np.vdot(S.conv3x3_circular(x, W), d)
+    rhs = np.vdot(x, S.conv3x3_adjoint(d, W))
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_train_loss_gradients_match_finite_differences():
+    """Unrounded network in FP64: every analytic gradient equals central differences of the loss."""
+    rng = np.random.default_rng(22)
+    K, N, M = 3, 8, 16
+    rms = rng.uniform(0.2, 0.6, K)
+    sigma = 5.0
+    cc = rng.standard_normal((K, N, M)) * 20.0 * rms[:, None, None]
+    cn = cc + rng.standard_normal((K, N, M)) * sigma * rms[:, None, None]
+    p = S.init_params(K, seed=23, tau0=2.0)
+    p.W3 *= 20.0
+    p.b1 += rng.standard_normal(32) * 0.1
+    p.b2 += rng.standard_normal(32) * 0.1
+    T, scale = 0.5, 1.0 / cn.size
+    L0, g = S.train_loss(cn, cc, sigma, rms, p, T, scale, rounded=False)
+    assert L0 > 0
+    for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        arr = getattr(p, name)
+        flat = arr.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            h = 1e-4 * max(1.0, abs(old))
+            flat[idx] = old + h
+            Lp, _ = S.train_loss(cn, cc, sigma, rms, p, T, scale, rounded=False)
+            flat[idx] = old - h
+            Lm, _ = S.train_loss(cn, cc, sigma, rms, p, T, scale, rounded=False)
+            flat[idx] = old
+            fd = (Lp - Lm) / (2 * h)
+            an = g[name].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(g[name]).max()), (name, idx, fd, an)
