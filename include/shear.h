@@ -184,6 +184,30 @@ int shear_shrink_pack(shear_system* s, const float* W1, const float* b1, const f
 int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, float* tau, int batch, const float* sigma,
                        const void* packed, void* hip_stream);
 
+/* Number of FP32 parameters of a K-filter network (577 K + 9280), or
+ * SHEAR_E_INVALID. Flat order: W1 [32][K][3][3], b1 [32], W2 [32][32][3][3],
+ * b2 [32], W3 [K][32][3][3], b3 [K]. */
+int shear_shrink_param_count(int K);
+
+/* One training step of the shrinkage network on a batch of coefficient
+ * pairs (c_noisy of images with noise sigma[b], c_clean of the same images
+ * without noise; both batch*K*rows*cols float32, device, as shear_forward
+ * writes them). The loss replaces the hard threshold by a smooth gate
+ * g = sigmoid((|z| - tau) / temperature) and is the mean over images, band
+ * planes and pixels of (z g - z_clean)^2, z the noise-normalised coefficients.
+ * Forward and backward run on the matrix cores (bfloat16 operands, FP32
+ * accumulation; the gradient planes are stored as bfloat16); the weight
+ * gradients are summed in a fixed order. Then one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected for `step` >= 1, rate lr) updates
+ * `params` (flat FP32, device), `grads` receives the gradients (same layout),
+ * `adam_state` holds the two moment vectors (2 x param count, zero before
+ * step 1) and `packed` is re-packed from the updated parameters. `loss`
+ * (one float, device) receives the loss of the step's forward pass.
+ * Asynchronous; uses the system's shrinkage workspace. */
+int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* c_clean, int batch, const float* sigma,
+                            float* params, float* grads, float* adam_state, void* packed, int step, float lr,
+                            float temperature, float* loss, void* hip_stream);
+
 /* Launch kinds reported by shear_profile_read (one kernel symbol each). */
 #define SHEAR_KERNEL_ROWS_R2C_IMAGES 0 /* forward: row FFT of the images              */
 #define SHEAR_KERNEL_COLS_FWD 1        /* forward: column FFT, x conj filter, IFFT (K-expanding) */

@@ -45,6 +45,8 @@ EXPORTED = (
     "shear_shrink_params_bytes",
     "shear_shrink_pack",
     "shear_shrink_apply",
+    "shear_shrink_param_count",
+    "shear_shrink_train_step",
     "shear_check",
     "shear_destroy_system",
     "shear_strerror",
@@ -110,6 +112,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shear_shrink_params_bytes.argtypes = [I, ctypes.POINTER(ctypes.c_size_t)]
     lib.shear_shrink_pack.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.shear_shrink_apply.argtypes = [P, P, P, P, I, P, P, P]
+    lib.shear_shrink_param_count.argtypes = [I]
+    lib.shear_shrink_train_step.argtypes = [P, P, P, I, P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, P, P]
     lib.shear_autotune.argtypes = [P, I, pI, pI]
     lib.shear_check.argtypes = [P, P]
     lib.shear_profile_enable.argtypes = [P, I]
@@ -426,12 +430,25 @@ class ShrinkNet:
         dev = device if device is not None else torch.device("cuda")
         K = system.K
         shapes = {"W1": (32, K, 3, 3), "b1": (32,), "W2": (32, 32, 3, 3), "b2": (32,), "W3": (K, 32, 3, 3), "b3": (K,)}
+        n = self._lib.shear_shrink_param_count(K)
+        if n < 0:
+            raise ShearError(n, "shear_shrink_param_count", f"unsupported filter count {K}")
+        # one flat FP32 buffer in the library's order; the named tensors are views of it
+        self.flat = torch.empty(n, dtype=torch.float32, device=dev)
         self.params = {}
-        for n in self.NAMES:
-            t = torch.as_tensor(params[n], dtype=torch.float32, device=dev).contiguous()
-            if tuple(t.shape) != shapes[n]:
-                raise ValueError(f"{n} has shape {tuple(t.shape)}, expected {shapes[n]}")
-            self.params[n] = t
+        o = 0
+        for name in self.NAMES:
+            t = torch.as_tensor(params[name], dtype=torch.float32, device=dev)
+            if tuple(t.shape) != shapes[name]:
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shapes[name]}")
+            view = self.flat[o:o + t.numel()].view(shapes[name])
+            view.copy_(t)
+            self.params[name] = view
+            o += t.numel()
+        assert o == n
+        self.grads = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.adam = torch.zeros(2 * n, dtype=torch.float32, device=dev)
+        self.steps = 0
         nb = ctypes.c_size_t()
         _check(self._lib.shear_shrink_params_bytes(K, ctypes.byref(nb)), "shear_shrink_params_bytes")
         self.packed = torch.empty(nb.value, dtype=torch.uint8, device=dev)
@@ -464,3 +481,35 @@ class ShrinkNet:
                                             ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(self.packed.data_ptr()),
                                             _stream_ptr(stream)), "shear_shrink_apply")
         return (out, t) if tau else out
+
+    def train_step(self, c_noisy, c_clean, sigma, lr: float, temperature: float = 0.5, stream=None):
+        """One Adam step on a batch of (noisy, clean) coefficient pairs (shear_shrink_train_step); returns the
+        step's loss as a one-element CUDA tensor (not synchronised)."""
+        import torch
+
+        s = self.system
+        B = c_noisy.shape[0]
+        s._check_tensor(c_noisy, (B, s.K, s.rows, s.cols), "c_noisy")
+        s._check_tensor(c_clean, (B, s.K, s.rows, s.cols), "c_clean")
+        sig = torch.as_tensor(sigma, dtype=torch.float32, device=c_noisy.device)
+        if sig.dim() == 0:
+            sig = sig.expand(B)
+        sig = sig.contiguous()
+        loss = torch.empty(1, dtype=torch.float32, device=c_noisy.device)
+        self.steps += 1
+        _check(self._lib.shear_shrink_train_step(
+            s._h, ctypes.c_void_p(c_noisy.data_ptr()), ctypes.c_void_p(c_clean.data_ptr()), B,
+            ctypes.c_void_p(sig.data_ptr()), ctypes.c_void_p(self.flat.data_ptr()), ctypes.c_void_p(self.grads.data_ptr()),
+            ctypes.c_void_p(self.adam.data_ptr()), ctypes.c_void_p(self.packed.data_ptr()), self.steps, float(lr),
+            float(temperature), ctypes.c_void_p(loss.data_ptr()), _stream_ptr(stream)), "shear_shrink_train_step")
+        return loss
+
+    def grad(self, name: str):
+        """The last step's gradient of one parameter (a view of the flat gradient buffer)."""
+        o = 0
+        for n in self.NAMES:
+            t = self.params[n]
+            if n == name:
+                return self.grads[o:o + t.numel()].view(t.shape)
+            o += t.numel()
+        raise KeyError(name)

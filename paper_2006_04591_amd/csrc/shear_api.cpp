@@ -229,9 +229,12 @@ int finish_system(shear_system* s, std::string& why) {
     s->filt_adj = base + b_tw + 2 * b_f;
     s->rms_dev = (const float*)(base + b_tw + 3 * b_f);
     s->fused = false;
+    if ((e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess) {
+        why = std::string("querying the compute-unit count failed: ") + hipGetErrorString(e);
+        return SHEAR_E_HIP;
+    }
     if (shear::fused_supported(N, M)) {
-        if ((e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess ||
-            (e = shear::fused_info(s->plan, true, s->finfo[0])) != hipSuccess ||
+        if ((e = shear::fused_info(s->plan, true, s->finfo[0])) != hipSuccess ||
             (e = shear::fused_info(s->plan, false, s->finfo[1])) != hipSuccess) {
             why = std::string("querying the fused kernels failed: ") + hipGetErrorString(e);
             return SHEAR_E_HIP;
@@ -1089,6 +1092,171 @@ int shear_shrink_pack(shear_system* s, const float* W1, const float* b1, const f
     return e == hipSuccess ? SHEAR_OK : hip_fail(e, "parameter packing launch");
 }
 
+namespace {
+
+int ensure_ws2(shear_system* s, size_t need) {
+    if (need <= s->ws2_bytes) return SHEAR_OK;
+    if (s->ws2) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before workspace growth");
+        (void)hipFree(s->ws2);
+        s->ws2 = nullptr;
+        s->ws2_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&s->ws2, need);
+    if (e != hipSuccess) {
+        s->ws2 = nullptr;
+        return fail(SHEAR_E_NOMEM, std::string("shrinkage workspace hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    s->ws2_bytes = need;
+    return SHEAR_OK;
+}
+
+size_t al256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+int shear_shrink_param_count(int K) { return (K >= 1 && K <= 64) ? 577 * K + 9280 : SHEAR_E_INVALID; }
+
+int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* c_clean, int batch, const float* sigma,
+                            float* params, float* grads, float* adam_state, void* packed, int step, float lr,
+                            float temperature, float* loss, void* stream) {
+    int rc = check_call(s, c_noisy, c_clean, batch);
+    if (rc != SHEAR_OK) return rc;
+    if (!sigma || !params || !grads || !adam_state || !packed || !loss)
+        return fail(SHEAR_E_INVALID, "NULL pointer argument");
+    if (step < 1 || !(temperature > 0.0f) || !(lr >= 0.0f))
+        return fail(SHEAR_E_INVALID, "step must be >= 1, temperature > 0 and lr >= 0");
+    if (!shear::shrink_supported(s->K, s->rows, s->cols))
+        return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 32 == 0");
+    const int K = s->K, N = s->rows, M = s->cols;
+    const int cpo = shear::shrink_cinp(K), c3 = shear::shrink_coutp(K);
+    const size_t pix = (size_t)batch * N * M;
+    const int ntiles = (int)(pix / (8 * 32));
+    const int G = std::max(1, std::min(ntiles, 2 * std::max(1, s->cus)));
+    const size_t part_stride = (size_t)std::max({32 * 9 * cpo + 32, c3 * 9 * 32 + c3, 32 * 9 * 32 + 32});
+    // workspace: scale | h1 | h2 | d o | dh2 | dh1 | transposed W3 | transposed W2 | partials
+    size_t off = 0;
+    const size_t o_sc = off;
+    off = al256(off + (size_t)batch * K * 4);
+    const size_t o_h1 = off;
+    off = al256(off + pix * 64);
+    const size_t o_h2 = off;
+    off = al256(off + pix * 64);
+    const size_t o_do = off;
+    off = al256(off + pix * cpo * 2);
+    const size_t o_dh2 = off;
+    off = al256(off + pix * 64);
+    const size_t o_dh1 = off;
+    off = al256(off + pix * 64);
+    const size_t o_t3 = off;
+    off = al256(off + (size_t)32 * 9 * cpo * 2);
+    const size_t o_t2 = off;
+    off = al256(off + (size_t)32 * 9 * 32 * 2);
+    const size_t o_part = off;
+    off = al256(off + (size_t)G * part_stride * 4);
+    if ((rc = ensure_ws2(s, off)) != SHEAR_OK) return rc;
+    char* w = (char*)s->ws2;
+    float* scale = (float*)(w + o_sc);
+    unsigned short* h1 = (unsigned short*)(w + o_h1);
+    unsigned short* h2 = (unsigned short*)(w + o_h2);
+    unsigned short* dO = (unsigned short*)(w + o_do);
+    unsigned short* dh2 = (unsigned short*)(w + o_dh2);
+    unsigned short* dh1 = (unsigned short*)(w + o_dh1);
+    unsigned short* t3 = (unsigned short*)(w + o_t3);
+    unsigned short* t2 = (unsigned short*)(w + o_t2);
+    float* part = (float*)(w + o_part);
+    // parameters, natural order, flat: W1 [32][K][3][3], b1 [32], W2 [32][32][3][3], b2 [32], W3 [K][32][3][3], b3 [K]
+    const size_t pW1 = 0, pb1 = 288 * (size_t)K, pW2 = pb1 + 32, pb2 = pW2 + 9216, pW3 = pb2 + 32, pb3 = pW3 + 288 * (size_t)K;
+    const int np = shear_shrink_param_count(K);
+    hipStream_t st = (hipStream_t)stream;
+    const shear::ShrinkLayout L = shear::shrink_layout(K);
+    const char* pk = (const char*)packed;
+    hipError_t e;
+    if ((e = shear::launch_zero_u32((unsigned*)loss, 1, st)) != hipSuccess) return hip_fail(e, "loss reset");
+    if ((e = shear::launch_inv_scale(sigma, s->rms_dev, scale, batch, K, st)) != hipSuccess) return hip_fail(e, "scale");
+    // forward: h1, h2 (as in inference), then the loss epilogue of the last layer
+    shear::ConvArgs a{};
+    a.N = N;
+    a.M = M;
+    a.scale = scale;
+    a.lowpass = K - 1;
+    a.in = c_noisy;
+    a.W = (const unsigned short*)(pk + L.w1);
+    a.bias = (const float*)(pk + L.b1);
+    a.out_bf = h1;
+    a.cin = K;
+    a.cout = 32;
+    if ((e = shear::launch_conv(0, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 1");
+    a.in = h1;
+    a.W = (const unsigned short*)(pk + L.w2);
+    a.bias = (const float*)(pk + L.b2);
+    a.out_bf = h2;
+    a.cin = 32;
+    if ((e = shear::launch_conv(1, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 2");
+    a.in = h2;
+    a.W = (const unsigned short*)(pk + L.w3);
+    a.bias = (const float*)(pk + L.b3);
+    a.out_bf = dO;
+    a.coef = c_noisy;
+    a.coef2 = c_clean;
+    a.loss = loss;
+    a.loss_scale = (float)(1.0 / ((double)batch * (K - 1 > 0 ? K - 1 : 1) * N * M));
+    a.temperature = temperature;
+    a.cout = K;
+    if ((e = shear::launch_conv(3, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 3 (loss)");
+    // backward: dW3, dh2, dW2, dh1, dW1
+    shear::WgradArgs g{};
+    g.batch = batch;
+    g.N = N;
+    g.M = M;
+    g.part = part;
+    g.scale = scale;
+    g.dy = dO;
+    g.dy_ch = cpo;
+    g.xb = h2;
+    if ((e = shear::launch_wgrad(2, K, g, G, st)) != hipSuccess) return hip_fail(e, "dW3");
+    if ((e = shear::launch_wgrad_reduce(part, grads + pW3, grads + pb3, G, K, 32, c3, 32, st)) != hipSuccess)
+        return hip_fail(e, "dW3 reduce");
+    if ((e = shear::launch_pack_weights_t(params + pW3, t3, K, 32, 32, cpo, st)) != hipSuccess) return hip_fail(e, "W3^T");
+    shear::ConvArgs bd{};
+    bd.N = N;
+    bd.M = M;
+    bd.in = dO;
+    bd.W = t3;
+    bd.mask_act = h2;
+    bd.out_bf = dh2;
+    if ((e = shear::launch_conv(5, K, bd, batch, st)) != hipSuccess) return hip_fail(e, "dh2");
+    g.dy = dh2;
+    g.dy_ch = 32;
+    g.xb = h1;
+    if ((e = shear::launch_wgrad(1, K, g, G, st)) != hipSuccess) return hip_fail(e, "dW2");
+    if ((e = shear::launch_wgrad_reduce(part, grads + pW2, grads + pb2, G, 32, 32, 32, 32, st)) != hipSuccess)
+        return hip_fail(e, "dW2 reduce");
+    if ((e = shear::launch_pack_weights_t(params + pW2, t2, 32, 32, 32, 32, st)) != hipSuccess) return hip_fail(e, "W2^T");
+    bd.in = dh2;
+    bd.W = t2;
+    bd.mask_act = h1;
+    bd.out_bf = dh1;
+    if ((e = shear::launch_conv(4, K, bd, batch, st)) != hipSuccess) return hip_fail(e, "dh1");
+    g.dy = dh1;
+    g.dy_ch = 32;
+    g.xf = c_noisy;
+    g.xb = nullptr;
+    g.cin = K;
+    if ((e = shear::launch_wgrad(0, K, g, G, st)) != hipSuccess) return hip_fail(e, "dW1");
+    if ((e = shear::launch_wgrad_reduce(part, grads + pW1, grads + pb1, G, 32, K, 32, cpo, st)) != hipSuccess)
+        return hip_fail(e, "dW1 reduce");
+    // Adam on the FP32 parameters, then the bfloat16 block
+    if ((e = shear::launch_adam(params, grads, adam_state, adam_state + np, np, lr, 0.9f, 0.999f, 1e-8f, step, st)) !=
+        hipSuccess)
+        return hip_fail(e, "Adam");
+    if ((e = shear::launch_shrink_pack(K, params + pW1, params + pb1, params + pW2, params + pb2, params + pW3,
+                                       params + pb3, packed, st)) != hipSuccess)
+        return hip_fail(e, "parameter packing");
+    return SHEAR_OK;
+}
+
 int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, float* tau, int batch, const float* sigma,
                        const void* packed, void* stream) {
     int rc = check_call(s, coeffs, shrunk, batch);
@@ -1099,22 +1267,7 @@ int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, floa
     const int K = s->K, N = s->rows, M = s->cols;
     const size_t act = (size_t)batch * N * M * 32 * 2;  // one bfloat16 activation tensor
     const size_t sc = ((size_t)batch * K * sizeof(float) + 255) & ~(size_t)255;
-    const size_t need = sc + 2 * act;
-    if (need > s->ws2_bytes) {
-        if (s->ws2) {
-            hipError_t e = hipDeviceSynchronize();
-            if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize before workspace growth");
-            (void)hipFree(s->ws2);
-            s->ws2 = nullptr;
-            s->ws2_bytes = 0;
-        }
-        hipError_t e = hipMalloc(&s->ws2, need);
-        if (e != hipSuccess) {
-            s->ws2 = nullptr;
-            return fail(SHEAR_E_NOMEM, std::string("shrinkage workspace hipMalloc failed: ") + hipGetErrorString(e));
-        }
-        s->ws2_bytes = need;
-    }
+    if ((rc = ensure_ws2(s, sc + 2 * act)) != SHEAR_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     char* w = (char*)s->ws2;
     float* scale = (float*)w;

@@ -25,6 +25,23 @@ struct ConvArgs {
     int N, M;
     int cin, cout;            // real channel counts (K for the coefficient side)
     int lowpass;
+    // training
+    const float* coef2;                // layer 2 training: coefficients of the clean images
+    const unsigned short* mask_act;    // backward data: saved activation whose relu mask applies
+    float* loss;                       // layer 2 training: sum of squared residuals (added)
+    float loss_scale, temperature;
+};
+
+// Weight-gradient launch: dy bf16 channel-last with dy_ch channels; input x either FP32 channel-first
+// coefficients (times scale, layer 0) or bf16 channel-last activations; per-block partials to part.
+struct WgradArgs {
+    const unsigned short* dy;
+    int dy_ch;
+    const float* xf;
+    const float* scale;
+    const unsigned short* xb;
+    float* part;
+    int batch, N, M, cin;
 };
 
 // Byte offsets of the packed parameter block of a K-filter network.
@@ -41,6 +58,16 @@ ShrinkLayout shrink_layout(int K);
 hipError_t launch_shrink_pack(int K, const float* W1, const float* b1, const float* W2, const float* b2,
                               const float* W3, const float* b3, void* packed, hipStream_t st);
 hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, int B, int K, hipStream_t st);
+// layer 0, 1, 2: inference layers; 3: last layer with the training epilogue; 4: backward data from 32
+// gradient channels; 5: backward data from shrink_cinp(K) gradient channels.
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st);
+// weight gradients of layer 0, 1 or 2 (partials of `blocks` blocks of 32-pixel x 8-row tiles)
+hipError_t launch_wgrad(int layer, int K, const WgradArgs& a, int blocks, hipStream_t st);
+hipError_t launch_wgrad_reduce(const float* part, float* dW, float* db, int nblk, int cout, int cin, int coutp, int cinp,
+                               hipStream_t st);
+hipError_t launch_pack_weights_t(const float* W, unsigned short* out, int cout, int cin, int rows, int cols,
+                                 hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t st);
 
 }  // namespace shear

@@ -48,10 +48,13 @@ struct Pix {
     static constexpr int value = CINP + 8;  // bf16 per staged pixel: 16 bytes of padding against bank conflicts
 };
 
-template <int CINP>
+// staged output channels: the 32 hidden channels, or the padded gradient planes of layer 2's training epilogue
+template <int CINP, int OUTC>
 constexpr size_t conv_lds_bytes() {
-    return (size_t)HH * HW * Pix<CINP>::value * 2 + (size_t)TH * TW * 32 * 2;
+    return (size_t)HH * HW * Pix<CINP>::value * 2 + (size_t)TH * TW * OUTC * 2;
 }
+
+__device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
 // Stages the halo tile of one image: MODE 0 from FP32 channel-first coefficient
 // planes (times scale[c], the noise normalisation), else from bfloat16
@@ -117,8 +120,12 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
 }
 
 // MODE 0: z (FP32 coefficients x scale) -> relu -> bf16 activations; MODE 1: activations -> relu -> activations;
-// MODE 2: activations -> o + b -> tau = softplus -> shrink of the coefficients.
-template <int CINP, int COUTP, int MODE>
+// MODE 2: activations -> o + b -> tau = softplus -> shrink of the coefficients;
+// MODE 3 (training, last layer): o -> smooth-gate loss (summed into *loss) and its gradient d o, stored as
+//   bf16 channel-last planes [b][y][x][OUTC] (zero beyond K and on the low-pass plane);
+// MODE 4 (training, backward data): gradient planes -> conv with flipped, transposed weights, times the relu
+//   mask of the saved activation (mask_act > 0) -> bf16 gradient activations.
+template <int CINP, int COUTP, int MODE, int OUTC = 32>
 __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     constexpr int NT = COUTP / 16;
     extern __shared__ unsigned short smem[];
@@ -156,25 +163,197 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
             }
         }
     } else {
-        // relu(acc + bias) -> bf16 through LDS, then 16-byte channel-last stores
+        // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel
+        float lsum = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int prow = (2 * w + mt / 2) * TW + (mt % 2) * 16 + lm;
+            const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int co = nt * 16 + lr;
-                const float bias = a.bias[co];
+                float v[4];
+                if constexpr (MODE == 3) {
+                    v[0] = v[1] = v[2] = v[3] = 0.0f;
+                    if (co < a.cout && co != a.lowpass) {
+                        const size_t off = (((size_t)b * a.cout + co) * a.N + y) * a.M + x;
+                        const float4 cn = *reinterpret_cast<const float4*>(a.coef + off);
+                        const float4 cc = *reinterpret_cast<const float4*>(a.coef2 + off);
+                        const float sc = a.scale[b * a.cout + co], bias = a.bias[co];
+                        const float n4[4] = {cn.x, cn.y, cn.z, cn.w}, c4[4] = {cc.x, cc.y, cc.z, cc.w};
 #pragma unroll
-                for (int i = 0; i < 4; ++i) s_out[(prow + i) * 32 + co] = f2bf(fmaxf(acc[mt][nt][i] + bias, 0.0f));
+                        for (int i = 0; i < 4; ++i) {
+                            const float o = acc[mt][nt][i] + bias;
+                            const float z = n4[i] * sc, zc = c4[i] * sc;
+                            const float g = sigmoidf((fabsf(z) - softplusf(o)) / a.temperature);
+                            const float r = z * g - zc;
+                            lsum += r * r;
+                            v[i] = 2.0f * a.loss_scale * r * z * g * (1.0f - g) * (-1.0f / a.temperature) * sigmoidf(o);
+                        }
+                    }
+                } else if constexpr (MODE == 4) {
+                    const unsigned short* h = a.mask_act + (((size_t)b * a.N + y) * a.M + x) * 32 + co;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = (bf2f(h[(size_t)i * 32]) > 0.0f) ? acc[mt][nt][i] : 0.0f;
+                } else {
+                    const float bias = a.bias[co];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = fmaxf(acc[mt][nt][i] + bias, 0.0f);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) s_out[(prow + i) * OUTC + co] = f2bf(v[i]);
             }
         }
+        if constexpr (OUTC > COUTP) {
+            for (int i = threadIdx.x; i < TH * TW * (OUTC - COUTP); i += THREADS)
+                s_out[(i / (OUTC - COUTP)) * OUTC + COUTP + i % (OUTC - COUTP)] = 0;
+        }
+        if constexpr (MODE == 3) {
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+            if (l == 0) atomicAdd(a.loss, lsum * a.loss_scale);
+        }
         __syncthreads();
+        constexpr int CH = OUTC / 8;
         uint4* out = reinterpret_cast<uint4*>(a.out_bf);
-        for (int i = threadIdx.x; i < TH * TW * 4; i += THREADS) {
-            const int ch = i % 4, p = i / 4, px = p % TW, py = p / TW;
-            out[(((size_t)b * a.N + y0 + py) * a.M + x0 + px) * 4 + ch] = *reinterpret_cast<const uint4*>(s_out + p * 32 + ch * 8);
+        for (int i = threadIdx.x; i < TH * TW * CH; i += THREADS) {
+            const int ch = i % CH, p = i / CH, px = p % TW, py = p / TW;
+            out[(((size_t)b * a.N + y0 + py) * a.M + x0 + px) * CH + ch] =
+                *reinterpret_cast<const uint4*>(s_out + p * OUTC + ch * 8);
         }
     }
+}
+
+// ---------------------------------------------------------------- weight gradients
+// dW[co][tap][ci] = sum over pixels p of dy[co](p) x[ci](p + tap offset): an MFMA GEMM with
+// M = output channels, N = (tap, input channel), K = pixels (one 32-pixel tile row per step).
+// A block loops over pixel tiles (stride gridDim.x) and writes its partial sums, and the bias
+// gradient sum_p dy[co](p), to part[blockIdx.x]; k_wgrad_reduce adds the partials in block order.
+// INMODE 0: x = bf16(coefficients x scale) (FP32 channel-first in); 1: bf16 channel-last activations.
+template <int CINP, int COUTP, int INMODE>
+__global__ __launch_bounds__(THREADS) void k_wgrad(WgradArgs a) {
+    constexpr int MT = COUTP / 16, NTT = 9 * CINP / 16, TT = MT * NTT, TPW = (TT + 3) / 4;
+    extern __shared__ unsigned short smem[];
+    unsigned short* s_dy = smem;                      // [COUTP][TH][TW]
+    unsigned short* s_x = smem + COUTP * TH * TW;     // [CINP][HH][HW]
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int lr = l % 16, lk = 8 * (l / 16);
+    const int N = a.N, M = a.M;
+    const int tx = M / TW, ty = N / TH, ntiles = a.batch * tx * ty;
+    f32x4 acc[TPW];
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) acc[j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    float bsum = 0.0f;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int bx = tile % tx, by = (tile / tx) % ty, b = tile / (tx * ty);
+        const int x0 = bx * TW, y0 = by * TH;
+        __syncthreads();  // the previous tile's LDS reads are done
+        // dy tile, channel-major
+        for (int i = threadIdx.x; i < COUTP * TH * TW; i += THREADS) {
+            const int px = i % TW, r = i / TW, py = r % TH, co = r / TH;
+            s_dy[i] = a.dy[(((size_t)b * N + y0 + py) * M + x0 + px) * a.dy_ch + co];
+        }
+        // input tile with halo, channel-major
+        for (int i = threadIdx.x; i < CINP * HH * HW; i += THREADS) {
+            const int xx = i % HW, r = i / HW, yy = r % HH, ci = r / HH;
+            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
+            unsigned short v = 0;
+            if constexpr (INMODE == 0) {
+                if (ci < a.cin)
+                    v = f2bf(a.xf[(((size_t)b * a.cin + ci) * N + y) * M + x] * a.scale[b * a.cin + ci]);
+            } else {
+                v = a.xb[(((size_t)b * N + y) * M + x) * CINP + ci];
+            }
+            s_x[i] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < COUTP) {
+            const unsigned short* d = s_dy + threadIdx.x * TH * TW;
+            for (int i = 0; i < TH * TW; ++i) bsum += bf2f(d[i]);
+        }
+#pragma unroll 1
+        for (int r = 0; r < TH; ++r) {
+#pragma unroll
+            for (int j = 0; j < TPW; ++j) {
+                const int t = w + 4 * j;
+                if (t < TT) {
+                    const int mt = t % MT, nt = t / MT;
+                    const int tap = nt / (CINP / 16), cg = nt % (CINP / 16);
+                    const int dy = tap / 3, dx = tap % 3;
+                    const bf16x8 afr = *reinterpret_cast<const bf16x8*>(s_dy + ((mt * 16 + lr) * TH + r) * TW + lk);
+                    const unsigned short* xp = s_x + ((cg * 16 + lr) * HH + r + dy) * HW + lk + dx;
+                    union {
+                        unsigned short u[8];
+                        bf16x8 v;
+                    } bb;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) bb.u[q] = xp[q];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bb.v, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // partial dW in [co][tap][ci] order, then the bias partial
+    float* part = a.part + (size_t)blockIdx.x * (COUTP * 9 * CINP + COUTP);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+        const int t = w + 4 * j;
+        if (t < TT) {
+            const int mt = t % MT, nt = t / MT;
+            const int tap = nt / (CINP / 16), ci = (nt % (CINP / 16)) * 16 + lr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = mt * 16 + 4 * (l / 16) + i;
+                part[((size_t)co * 9 + tap) * CINP + ci] = acc[j][i];
+            }
+        }
+    }
+    if (threadIdx.x < COUTP) part[COUTP * 9 * CINP + threadIdx.x] = bsum;
+}
+
+// grads in natural order: dW[co][ci][3][3] (co < cout, ci < cin), then db[co]; sums of nblk partials in order
+__global__ void k_wgrad_reduce(const float* __restrict__ part, float* __restrict__ dW, float* __restrict__ db, int nblk,
+                               int cout, int cin, int coutp, int cinp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nw = cout * cin * 9;
+    if (i >= nw + cout) return;
+    size_t src;
+    if (i < nw) {
+        const int tap = i % 9, ci = (i / 9) % cin, co = i / (9 * cin);
+        src = ((size_t)co * 9 + tap) * cinp + ci;
+    } else {
+        src = (size_t)coutp * 9 * cinp + (i - nw);
+    }
+    const size_t stride = (size_t)coutp * 9 * cinp + coutp;
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[(size_t)b * stride + src];
+    if (i < nw)
+        dW[i] = s;
+    else
+        db[i - nw] = s;
+}
+
+// natural W[co][ci][3][3] -> flipped, transposed bf16 [ci][8 - tap][co], padded to cinp' x coutp'
+// (the weights of the backward-data correlation)
+__global__ void k_pack_weights_t(const float* __restrict__ W, unsigned short* __restrict__ out, int cout, int cin,
+                                 int rows, int cols) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * 9 * cols) return;
+    const int co = i % cols, tap = (i / cols) % 9, ci = i / (cols * 9);
+    out[i] = (ci < cin && co < cout) ? f2bf(W[((size_t)co * cin + ci) * 9 + (8 - tap)]) : (unsigned short)0;
+}
+
+// Adam (bias-corrected) on n FP32 parameters; step t >= 1
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
 // inverse noise scale per (image, filter): 1 / (sigma_b RMS_k)
@@ -198,16 +377,28 @@ __global__ void k_pack_bias(const float* __restrict__ b, float* __restrict__ out
     if (i < np) out[i] = i < n ? b[i] : 0.0f;
 }
 
-template <int CINP, int COUTP, int MODE>
+template <int CINP, int COUTP, int MODE, int OUTC = 32>
 hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
-    const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE>);
-    const size_t lds = conv_lds_bytes<CINP>();
+    const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC>);
+    const size_t lds = conv_lds_bytes<CINP, OUTC>();
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const size_t blocks = (size_t)batch * (a.N / TH) * (a.M / TW);
-    hipLaunchKernelGGL((k_conv3x3<CINP, COUTP, MODE>), dim3((unsigned)blocks), dim3(THREADS), lds, st, a);
+    hipLaunchKernelGGL((k_conv3x3<CINP, COUTP, MODE, OUTC>), dim3((unsigned)blocks), dim3(THREADS), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int CINP, int COUTP, int INMODE>
+hipError_t wgrad_t(const WgradArgs& a, int blocks, hipStream_t st) {
+    const void* fn = reinterpret_cast<const void*>(&k_wgrad<CINP, COUTP, INMODE>);
+    const size_t lds = ((size_t)COUTP * TH * TW + (size_t)CINP * HH * HW) * 2;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_wgrad<CINP, COUTP, INMODE>), dim3((unsigned)blocks), dim3(THREADS), lds, st, a);
     return hipGetLastError();
 }
 
@@ -261,6 +452,22 @@ hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, in
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st) {
     if (layer == 0) return shrink_cinp(K) == 32 ? conv_t<32, 32, 0>(a, batch, st) : conv_t<64, 32, 0>(a, batch, st);
     if (layer == 1) return conv_t<32, 32, 1>(a, batch, st);
+    if (layer == 3) {  // training: last layer with the loss epilogue, gradient planes of shrink_cinp(K) channels
+        if (shrink_cinp(K) == 32) {
+            switch (shrink_coutp(K)) {
+                case 16: return conv_t<32, 16, 3, 32>(a, batch, st);
+                case 32: return conv_t<32, 32, 3, 32>(a, batch, st);
+            }
+        } else {
+            switch (shrink_coutp(K)) {
+                case 48: return conv_t<32, 48, 3, 64>(a, batch, st);
+                case 64: return conv_t<32, 64, 3, 64>(a, batch, st);
+            }
+        }
+        return hipErrorInvalidValue;
+    }
+    if (layer == 4) return conv_t<32, 32, 4>(a, batch, st);  // backward data from 32 gradient channels
+    if (layer == 5) return shrink_cinp(K) == 32 ? conv_t<32, 32, 4>(a, batch, st) : conv_t<64, 32, 4>(a, batch, st);
     switch (shrink_coutp(K)) {
         case 16: return conv_t<32, 16, 2>(a, batch, st);
         case 32: return conv_t<32, 32, 2>(a, batch, st);
@@ -268,6 +475,46 @@ hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream
         case 64: return conv_t<32, 64, 2>(a, batch, st);
     }
     return hipErrorInvalidValue;
+}
+
+}  // namespace shear
+
+namespace shear {
+
+hipError_t launch_wgrad(int layer, int K, const WgradArgs& a, int blocks, hipStream_t st) {
+    if (layer == 0) return shrink_cinp(K) == 32 ? wgrad_t<32, 32, 0>(a, blocks, st) : wgrad_t<64, 32, 0>(a, blocks, st);
+    if (layer == 1) return wgrad_t<32, 32, 1>(a, blocks, st);
+    switch (shrink_coutp(K)) {
+        case 16: return wgrad_t<32, 16, 1>(a, blocks, st);
+        case 32: return wgrad_t<32, 32, 1>(a, blocks, st);
+        case 48: return wgrad_t<32, 48, 1>(a, blocks, st);
+        case 64: return wgrad_t<32, 64, 1>(a, blocks, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_wgrad_reduce(const float* part, float* dW, float* db, int nblk, int cout, int cin, int coutp, int cinp,
+                               hipStream_t st) {
+    const int n = cout * cin * 9 + cout;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, dW, db, nblk, cout, cin,
+                       coutp, cinp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_weights_t(const float* W, unsigned short* out, int cout, int cin, int rows, int cols,
+                                 hipStream_t st) {
+    const int n = rows * 9 * cols;
+    hipLaunchKernelGGL(k_pack_weights_t, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, W, out, cout, cin, rows,
+                       cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t st) {
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1,
+                       c2);
+    return hipGetLastError();
 }
 
 }  // namespace shear
