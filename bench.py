@@ -252,6 +252,132 @@ def bench_inpaint(args) -> int:
     return 0
 
 
+METRIC_SHRINK = "learned-shrinkage denoising (fwd + bf16-MFMA shrink network + inv) Mpix·filters/s @512²×49"
+
+
+def bench_shrink(args) -> int:
+    """Learned shrinkage: a 3-layer 3x3 network (49 -> 32 -> 32 -> 49, bf16 matrix-core kernels, FP32
+    accumulate) is trained on generated (image, noise) pairs: a seeded pool of 32 clean 512x512 cartoons, each
+    step draws 16 of them with noise levels sigma ~ U[10, 50] and fresh noise (seeded), 1250 steps = 20k pairs.
+    It is then judged on 16 held-out noisy images against plain hard thresholding (3 sigma RMS_k), by PSNR.
+    One timed step = forward transform + shrink network + inverse transform of the 16 held-out images."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    dev = torch.device("cuda:0")
+    shs = ShearletSystem.build(N, M, J)
+    K = shs.K
+    shs.reserve(B)
+    schedule = shs.autotune(B)
+    pool = torch.from_numpy(np.stack([synth.cartoon(N, M, seed=5000 + i) for i in range(32)])).to(dev)
+    rng = np.random.default_rng(5)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5)
+    # initial parameters: small random weights, output bias giving tau = 3 (hard thresholding at 3 sigma)
+    r0 = np.random.default_rng(6)
+
+    def he(co, ci):
+        return (r0.standard_normal((co, ci, 3, 3)) * np.sqrt(2.0 / (9 * ci))).astype(np.float32)
+
+    params = {"W1": he(32, K), "b1": np.zeros(32, np.float32), "W2": he(32, 32), "b2": np.zeros(32, np.float32),
+              "W3": 0.1 * he(K, 32), "b3": np.full(K, np.log(np.expm1(3.0)), np.float32)}
+    net = ShrinkNet(shs, params)
+    cn = torch.empty((B, K, N, M), dtype=torch.float32, device=dev)
+    cc = torch.empty_like(cn)
+    steps_train = int(args.train_steps)
+    t0 = time.perf_counter()
+    losses = []
+    for it in range(steps_train):
+        idx = torch.from_numpy(rng.integers(0, 32, size=B)).to(dev)
+        sig = torch.from_numpy(rng.uniform(10.0, 50.0, size=B).astype(np.float32)).to(dev)
+        clean = pool[idx]
+        noisy = clean + sig[:, None, None] * torch.randn((B, N, M), generator=gen, device=dev)
+        shs.forward(noisy, out=cn)
+        shs.forward(clean, out=cc)
+        lr = 2e-3 if it < steps_train // 2 else 5e-4
+        loss = net.train_step(cn, cc, sig, lr=lr, temperature=0.5)
+        if it % 250 == 0 or it == steps_train - 1:
+            losses.append((it, float(loss)))
+            log(f"bench shrink: step {it} loss {losses[-1][1]:.5f} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    # held-out test set
+    sig_t = rng.uniform(10.0, 50.0, size=B).astype(np.float32)
+    clean_t = np.stack([synth.cartoon(N, M, seed=5500 + i) for i in range(B)])
+    noisy_t = np.stack([clean_t[i] + synth.gaussian_noise(N, M, float(sig_t[i]), seed=6000 + i) for i in range(B)])
+    x = torch.from_numpy(noisy_t).to(dev)
+    sg = torch.from_numpy(sig_t).to(dev)
+    c = torch.empty((B, K, N, M), dtype=torch.float32, device=dev)
+    cs = torch.empty_like(c)
+    y = torch.empty((B, N, M), dtype=torch.float32, device=dev)
+
+    def step():
+        shs.forward(x, out=c)
+        net.apply(c, sg, out=cs)
+        shs.inverse(cs, out=y)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    shs.profile(True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    rec = shs.profile_read()
+    shs.profile(False)
+    # the network's kernels are timed apart, same stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        net.apply(c, sg, out=cs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_net = e0.elapsed_time(e1) / args.steps
+    yl = y.cpu().numpy()
+    thr = torch.from_numpy(np.stack([shs.paper_thresholds(float(sig_t[i]), factors=[3.0] * J) for i in range(B)])).to(dev)
+    yh = shs.denoise(x, thr).cpu().numpy()
+
+    def psnr(a, b):
+        d = np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)
+        return float(20.0 * np.log10(255.0 * np.sqrt(d.size) / np.linalg.norm(d)))
+
+    p_learned = [psnr(clean_t[i], yl[i]) for i in range(B)]
+    p_hard = [psnr(clean_t[i], yh[i]) for i in range(B)]
+    p_noisy = [psnr(clean_t[i], noisy_t[i]) for i in range(B)]
+    flops = 2.0 * B * N * M * 9 * (32 * K + 32 * 32 + K * 32)  # the three layers, real channels
+    net_tflops = flops / (ms_net / 1e3) / 1e12
+    units = B * N * M * K / 1e6
+    res = {
+        "metric": METRIC_SHRINK, "value": units / (ms_step / 1e3), "unit": "Mpix·filters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16 (network) / f32 (transform)", "data": "synthetic",
+        "config": {"workload": "learned shrinkage, 16 held-out 512x512 cartoons, sigma ~ U[10,50], 49 filters; "
+                               "network 49-32-32-49, 3x3, trained on 20k generated pairs",
+                   "batch": B, "rows": N, "cols": M, "filters": K, "train_steps": steps_train,
+                   "train_pairs": steps_train * B, "column_schedule": list(schedule)},
+        "roofline": {"bound": "mfma", "achieved": net_tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": net_tflops / 2500.0, "traffic": None, "kernel": "shrink network (3 layers)",
+                     "avg_launch_ms": ms_net, "flops_per_launch": flops},
+        "kernels": {k: {"launches": n, "avg_ms": t / n} for k, (n, t) in rec.items() if n},
+        "train_seconds": train_s, "train_losses": losses,
+        "psnr_noisy_mean_db": float(np.mean(p_noisy)), "psnr_hard_mean_db": float(np.mean(p_hard)),
+        "psnr_learned_mean_db": float(np.mean(p_learned)),
+        "learned_beats_hard": bool(np.mean(p_learned) > np.mean(p_hard)),
+    }
+    shs.close()
+    print(json.dumps(res))
+    return 0
+
+
 def copy_calibration(mib: int) -> int:
     """Device-to-device copies of a known size, to calibrate rocprofv3 FETCH_SIZE / WRITE_SIZE."""
     import torch
@@ -333,20 +459,22 @@ def main() -> int:
     ap.add_argument("--fpb", type=int, default=0, help="pipeline: filters per column block (0 = library default)")
     ap.add_argument("--chunk-images", type=int, default=0,
                     help="images per chunk of the K-expanded intermediate (0 = whole batch)")
-    ap.add_argument("--workload", default="fwdinv", choices=("fwdinv", "denoise", "layer", "inpaint"),
+    ap.add_argument("--train-steps", type=int, default=1250, help="shrink: training steps (16 pairs each)")
+    ap.add_argument("--workload", default="fwdinv", choices=("fwdinv", "denoise", "layer", "inpaint", "shrink"),
                     help="fwdinv: shear_forward + shear_inverse (the headline); denoise: shear_denoise with the "
                          "paper's thresholds (Section 4.2); layer: the autograd layer's forward and backward at "
-                         "32 x 256x256, 33 filters; inpaint: Algorithm 3 on 8 images of uneven sizes")
+                         "32 x 256x256, 33 filters; inpaint: Algorithm 3 on 8 images of uneven sizes; shrink: train and run "
+                         "the learned shrinkage network")
     args = ap.parse_args()
     denoise = args.workload == "denoise"
     layer = args.workload == "layer"
-    if args.workload == "inpaint":
+    if args.workload in ("inpaint", "shrink"):
         import torch
 
         if not torch.cuda.is_available():
             print("bench.py: no GPU visible", file=sys.stderr)
             return 2
-        return bench_inpaint(args)
+        return bench_inpaint(args) if args.workload == "inpaint" else bench_shrink(args)
     global B, N, M, J, SHEAR_LEVELS, CONFIG_ID
     if layer:
         B, N, M, J, SHEAR_LEVELS, CONFIG_ID = 32, 256, 256, 3, [1, 1, 2], 4
