@@ -304,8 +304,8 @@ def bench_shrink(args) -> int:
             log(f"bench shrink: step {it} loss {losses[-1][1]:.5f} ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    # held-out test set
-    sig_t = rng.uniform(10.0, 50.0, size=B).astype(np.float32)
+    # held-out test set (its own seeds: independent of the number of training steps)
+    sig_t = np.random.default_rng(7).uniform(10.0, 50.0, size=B).astype(np.float32)
     clean_t = np.stack([synth.cartoon(N, M, seed=5500 + i) for i in range(B)])
     noisy_t = np.stack([clean_t[i] + synth.gaussian_noise(N, M, float(sig_t[i]), seed=6000 + i) for i in range(B)])
     x = torch.from_numpy(noisy_t).to(dev)
