@@ -260,19 +260,25 @@ int shear_profile_read(shear_system* s, int* launches, double* total_ms);
 int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_block);
 
 /* Column-pass schedule of the separate-launch kernels: pw_fwd / pw_inv
- * columns per block (16 or 8; 16 needs cols >= 32; 0 keeps the current value)
- * in the forward and in the inverse/adjoint column passes. Results do not
- * depend on it (every column is transformed by the same operations); speed
- * does. SHEAR_E_INVALID for other values. */
-int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv);
+ * columns per block (16 or 8; 16 needs cols >= 32) and kg_fwd / kg_inv
+ * filter groups (1..K: the K filters of a column panel are split over that
+ * many blocks, so that small batches fill the device; the inverse then adds
+ * the groups' partial sums in group order), in the forward and in the
+ * inverse/adjoint column passes; 0 keeps the current value. The forward's
+ * results do not depend on the schedule (every column and filter goes
+ * through the same operations); the inverse's summation order over the
+ * filters follows the groups, so it agrees to rounding. SHEAR_E_INVALID for
+ * other values. Drops any captured inpainting graph. */
+int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv);
 
 /* Autotuner: times the column passes of both directions for every compiled
- * panel width on the system's workspace at this batch size (clearing the
- * workspace first), keeps the fastest (shear_set_schedule) and reports it
- * through pw_fwd / pw_inv (either may be NULL). Synchronous: waits for the
- * device, allocates the workspace for batch if needed, uses the null stream.
- * Drops any captured inpainting graph. */
-int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv);
+ * panel width and filter split in {1, 2, 4, 8} (at most K) on the system's
+ * workspace at this batch size (clearing the workspace first), keeps the
+ * fastest of each direction (shear_set_schedule) and reports it through the
+ * out-pointers (any may be NULL). Synchronous: waits for the device,
+ * allocates the workspace for batch if needed, uses the null stream. Drops
+ * any captured inpainting graph. */
+int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv);
 
 /* Waits for hip_stream, then reports SHEAR_E_HIP if the last fused launch of
  * the system gave up on a dependency wait (its output is then invalid). The

@@ -108,13 +108,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
     lib.shear_set_path.argtypes = [P, I, I, I]
-    lib.shear_set_schedule.argtypes = [P, I, I]
+    lib.shear_set_schedule.argtypes = [P, I, I, I, I]
     lib.shear_shrink_params_bytes.argtypes = [I, ctypes.POINTER(ctypes.c_size_t)]
     lib.shear_shrink_pack.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.shear_shrink_apply.argtypes = [P, P, P, P, I, P, P, P]
     lib.shear_shrink_param_count.argtypes = [I]
     lib.shear_shrink_train_step.argtypes = [P, P, P, I, P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, P, P]
-    lib.shear_autotune.argtypes = [P, I, pI, pI]
+    lib.shear_autotune.argtypes = [P, I, pI, pI, pI, pI]
     lib.shear_check.argtypes = [P, P]
     lib.shear_profile_enable.argtypes = [P, I]
     lib.shear_profile_read.argtypes = [P, pI, pD]
@@ -366,16 +366,18 @@ class ShearletSystem:
         _check(self._lib.shear_set_path(self._h, self.PATHS[path], int(chunk_images), int(filters_per_block)),
                "shear_set_path")
 
-    def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0) -> None:
-        """Columns per block of the forward and inverse column passes (shear_set_schedule)."""
-        _check(self._lib.shear_set_schedule(self._h, int(pw_fwd), int(pw_inv)), "shear_set_schedule")
+    def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0, kg_fwd: int = 0, kg_inv: int = 0) -> None:
+        """Columns per block and filter groups of the forward and inverse column passes (shear_set_schedule);
+        0 keeps a value."""
+        _check(self._lib.shear_set_schedule(self._h, int(pw_fwd), int(pw_inv), int(kg_fwd), int(kg_inv)),
+               "shear_set_schedule")
 
     def autotune(self, batch: int):
         """Times the compiled column-pass schedules at this batch size and keeps the fastest
-        (shear_autotune); returns (pw_fwd, pw_inv)."""
-        a, b = ctypes.c_int(), ctypes.c_int()
-        _check(self._lib.shear_autotune(self._h, int(batch), ctypes.byref(a), ctypes.byref(b)), "shear_autotune")
-        return a.value, b.value
+        (shear_autotune); returns (pw_fwd, pw_inv, kg_fwd, kg_inv)."""
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(self._lib.shear_autotune(self._h, int(batch), *[ctypes.byref(x) for x in v]), "shear_autotune")
+        return tuple(x.value for x in v)
 
     def check(self, stream=None) -> None:
         """Waits for the stream and raises if the last fused launch gave up on a dependency (shear_check)."""

@@ -17,7 +17,18 @@ struct DevPlan {
     const float2* twM = nullptr;  // exp(-2 pi i m / M), m < M
     int pw_fwd = 16;          // columns per block of the column passes (16 or 8; 8 when L < 16)
     int pw_inv = 16;
+    int kg_fwd = 1;           // filter groups of the column passes (blocks per panel; capped at K)
+    int kg_inv = 1;
 };
+
+// Partial-sum scratch of the inverse column pass for nimg images (float2 elements; 0 when kg_inv is 1).
+inline size_t cols_inv_part_elems(const DevPlan& d, int nimg) {
+    int kg = d.kg_inv < 1 ? 1 : (d.kg_inv > d.K ? d.K : d.kg_inv);
+    if (kg <= 1) return 0;
+    const int kper = (d.K + kg - 1) / kg;
+    kg = (d.K + kper - 1) / kper;
+    return kg <= 1 ? 0 : (size_t)nimg * kg * ((size_t)d.L * d.N + d.N);
+}
 
 // coeff_planes selects a separate kernel symbol for coefficient planes (same code).
 // Rows (real, row-major planes x N x M) -> packed row spectra, column-major
@@ -46,7 +57,9 @@ hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nim
                            hipStream_t st);
 
 // Inverse / adjoint, column stage, K-reducing: V[b] = colIFFT( sum_k filt_k (.) colFFT(U[b][k]) ).
-hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, hipStream_t st);
+// part: cols_inv_part_elems(d, nimg) float2 of scratch (may be null when that is 0).
+hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
+                           hipStream_t st);
 
 bool size_supported(int n);
 

@@ -656,36 +656,94 @@ struct ColCfg {
     static constexpr size_t LDS = ((size_t)PW * ColScratch<N, P>::value + N) * sizeof(float2);
 };
 
+// Filter groups: the K filters of a column panel may be split over kg blocks of kper
+// consecutive filters (block index = pan + npan (g + kg b)), so that small batches still
+// fill the device. The forward recomputes the panel's column FFT in each group; the
+// inverse writes one partial sum per group and k_cols_inv_finish adds them in group order.
 template <int N, int PW, bool REAL>
 __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const float2* __restrict__ A,
                                                                     float2* __restrict__ Tout,
                                                                     const void* __restrict__ filt, int L, int K,
-                                                                    int npan, const float2* __restrict__ twN,
-                                                                    float scale) {
+                                                                    int npan, int kper, int kg,
+                                                                    const float2* __restrict__ twN, float scale) {
     constexpr int P = ColCfg<N, PW>::P;
     extern __shared__ float2 lds[];
-    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
+    const int pan = blockIdx.x % npan, g = (blockIdx.x / npan) % kg, b = blockIdx.x / (npan * kg);
     float2 xh[P];
     col_fwd_setup<N, P, PW>(A + (size_t)b * L * N, pan * PW, xh, lds, scale, twN, (int)threadIdx.x);
-    for (int k = 0; k < K; ++k)
-        col_fwd_emit<N, P, PW, REAL>(xh, filt, k, L, pan * PW, Tout + ((size_t)b * K + k) * L * N, lds, twN, (int)threadIdx.x);
+    const int k1 = min(K, (g + 1) * kper);
+    for (int k = g * kper; k < k1; ++k)
+        col_fwd_emit<N, P, PW, REAL>(xh, filt, k, L, pan * PW, Tout + ((size_t)b * K + k) * L * N, lds, twN,
+                                     (int)threadIdx.x);
 }
 
+// kg == 1: V[b] = colIFFT(sum_k ...); kg > 1: part[b][g] (L x N column-major) and, for packed
+// column 0, part0[b][g] (N) receive the group's sums.
 template <int N, int PW, bool REAL>
 __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const float2* __restrict__ U,
                                                                     float2* __restrict__ V,
                                                                     const void* __restrict__ filt, int L, int K,
-                                                                    int npan, const float2* __restrict__ twN) {
-    constexpr int P = ColCfg<N, PW>::P;
+                                                                    int npan, int kper, int kg,
+                                                                    float2* __restrict__ part,
+                                                                    float2* __restrict__ part0,
+                                                                    const float2* __restrict__ twN) {
+    constexpr int P = ColCfg<N, PW>::P, T = N / P;
     extern __shared__ float2 lds[];
-    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
+    const int pan = blockIdx.x % npan, g = (blockIdx.x / npan) % kg, b = blockIdx.x / (npan * kg);
     const int tid = (int)threadIdx.x;
     float2 acc[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) acc[q] = make_float2(0.0f, 0.0f);
     col_inv_begin<N, P, PW>(pan * PW, lds, tid);
-    for (int k = 0; k < K; ++k)
+    const int k1 = min(K, (g + 1) * kper);
+    for (int k = g * kper; k < k1; ++k)
         col_inv_accum<N, P, PW, REAL>(U + ((size_t)b * K + k) * L * N, filt, k, L, pan * PW, acc, lds, twN, tid);
+    if (kg == 1) {
+        col_inv_finish<N, P, PW>(acc, pan * PW, V + (size_t)b * L * N, lds, twN, tid);
+        return;
+    }
+    const int t = tid % T, c = tid / T, col = pan * PW + c;
+    float2* o = part + ((size_t)b * kg + g) * L * N + (size_t)col * N;
+#pragma unroll
+    for (int q = 0; q < P; ++q) o[t + T * q] = acc[q];
+    if (col == 0) {
+        // each thread of column 0 reads back the entries of the mirrored-term sum it accumulated
+        const float2* sg = lds + PW * ColScratch<N, P>::value;
+        float2* og = part0 + ((size_t)b * kg + g) * N;
+#pragma unroll
+        for (int q = 0; q < P; ++q) og[t + T * q] = sg[t + T * q];
+    }
+}
+
+// V[b] panel = colIFFT(sum_g part[b][g] [+ conj of the mirrored column-0 partials]), g in order
+template <int N, int PW>
+__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv_finish(const float2* __restrict__ part,
+                                                                           const float2* __restrict__ part0,
+                                                                           float2* __restrict__ V, int L, int npan,
+                                                                           int kg, const float2* __restrict__ twN) {
+    constexpr int P = ColCfg<N, PW>::P, T = N / P;
+    extern __shared__ float2 lds[];
+    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
+    const int tid = (int)threadIdx.x;
+    const int t = tid % T, c = tid / T, col = pan * PW + c;
+    float2 acc[P], gg[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) acc[q] = gg[q] = make_float2(0.0f, 0.0f);
+    for (int g = 0; g < kg; ++g) {
+        const float2* src = part + ((size_t)b * kg + g) * L * N + (size_t)col * N;
+#pragma unroll
+        for (int q = 0; q < P; ++q) acc[q] = cadd(acc[q], src[t + T * q]);
+        if (col == 0) {
+            const float2* sg = part0 + ((size_t)b * kg + g) * N;
+#pragma unroll
+            for (int q = 0; q < P; ++q) gg[q] = cadd(gg[q], sg[t + T * q]);
+        }
+    }
+    if (col == 0) {
+        float2* smir = lds + PW * ColScratch<N, P>::value;
+#pragma unroll
+        for (int q = 0; q < P; ++q) smir[t + T * q] = gg[q];
+    }
     col_inv_finish<N, P, PW>(acc, pan * PW, V + (size_t)b * L * N, lds, twN, tid);
 }
 
@@ -1085,42 +1143,62 @@ hipError_t rows_thresh_t(const DevPlan& d, float2* planes, int nplanes, const fl
     return hipGetLastError();
 }
 
+// filters per group for kg requested groups, and the groups that gives
+inline void kgroups(int K, int kg_req, int& kper, int& kg) {
+    kg_req = std::max(1, std::min(kg_req, K));
+    kper = (K + kg_req - 1) / kg_req;
+    kg = (K + kper - 1) / kper;
+}
+
 template <int N, int PW>
 hipError_t cols_fwd_t(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
                       hipStream_t st) {
     using C = ColCfg<N, PW>;
     const int npan = d.L / PW;
-    const size_t blocks = (size_t)npan * nimg;
+    int kper, kg;
+    kgroups(d.K, d.kg_fwd, kper, kg);
+    const size_t blocks = (size_t)npan * kg * nimg;
     if (d.real) {
         hipError_t e = set_lds(k_cols_fwd<N, PW, true>, C::LDS);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_cols_fwd<N, PW, true>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, A, T,
-                           filt, d.L, d.K, npan, d.twN, scale);
+                           filt, d.L, d.K, npan, kper, kg, d.twN, scale);
     } else {
         hipError_t e = set_lds(k_cols_fwd<N, PW, false>, C::LDS);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_cols_fwd<N, PW, false>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, A, T,
-                           filt, d.L, d.K, npan, d.twN, scale);
+                           filt, d.L, d.K, npan, kper, kg, d.twN, scale);
     }
     return hipGetLastError();
 }
 
 template <int N, int PW>
-hipError_t cols_inv_t(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, hipStream_t st) {
+hipError_t cols_inv_t(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
+                      hipStream_t st) {
     using C = ColCfg<N, PW>;
     const int npan = d.L / PW;
-    const size_t blocks = (size_t)npan * nimg;
+    int kper, kg;
+    kgroups(d.K, d.kg_inv, kper, kg);
+    if (kg > 1 && part == nullptr) return hipErrorInvalidValue;
+    float2* part0 = kg > 1 ? part + (size_t)nimg * kg * d.L * d.N : nullptr;
+    const size_t blocks = (size_t)npan * kg * nimg;
     if (d.real) {
         hipError_t e = set_lds(k_cols_inv<N, PW, true>, C::LDS);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_cols_inv<N, PW, true>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, U, V,
-                           filt, d.L, d.K, npan, d.twN);
+                           filt, d.L, d.K, npan, kper, kg, part, part0, d.twN);
     } else {
         hipError_t e = set_lds(k_cols_inv<N, PW, false>, C::LDS);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_cols_inv<N, PW, false>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, U, V,
-                           filt, d.L, d.K, npan, d.twN);
+                           filt, d.L, d.K, npan, kper, kg, part, part0, d.twN);
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || kg == 1) return e;
+    e = set_lds(k_cols_inv_finish<N, PW>, C::LDS);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cols_inv_finish<N, PW>), dim3((unsigned)((size_t)npan * nimg)), dim3(C::THREADS), C::LDS, st,
+                       part, part0, V, d.L, npan, kg, d.twN);
     return hipGetLastError();
 }
 
@@ -1223,8 +1301,9 @@ hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nim
     SHEAR_COLS_SWITCH(d.pw_fwd, cols_fwd_t, d, A, T, nimg, filt, scale, st)
 }
 
-hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, hipStream_t st) {
-    SHEAR_COLS_SWITCH(d.pw_inv, cols_inv_t, d, U, V, nimg, filt, st)
+hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
+                           hipStream_t st) {
+    SHEAR_COLS_SWITCH(d.pw_inv, cols_inv_t, d, U, V, nimg, filt, part, st)
 }
 
 // ---------------------------------------------------------------- fused dispatch

@@ -316,18 +316,27 @@ size_t fused_ws_needed(const shear_system* s, const shear::FusedGeom& g) {
            ((shear::fused_ctr_words(g) * sizeof(unsigned) + 255) & ~(size_t)255);
 }
 
+// Separate-path workspace: [batch planes A or V][chunk x K exchange planes][inverse partial sums of chunk images].
+size_t part_bytes(const shear_system* s, int chunk) { return shear::cols_inv_part_elems(s->plan, chunk) * sizeof(float2); }
+
 // Images per chunk of the K-expanded intermediate, or 0 if even one does not fit.
 int chunk_images(const shear_system* s, int batch) {
     const size_t pb = plane_bytes(s);
     const size_t fixed = (size_t)batch * pb;
     if (fixed >= s->ws_cap) return 0;
-    const size_t per = (size_t)s->K * pb;
+    const size_t per = (size_t)s->K * pb + part_bytes(s, 1);
     const size_t n = (s->ws_cap - fixed) / per;
     return (int)std::min<size_t>(n, (size_t)batch);
 }
 
 size_t ws_needed(const shear_system* s, int batch, int chunk) {
-    return (size_t)batch * plane_bytes(s) + (size_t)chunk * s->K * plane_bytes(s);
+    return (size_t)batch * plane_bytes(s) + (size_t)chunk * s->K * plane_bytes(s) + part_bytes(s, chunk);
+}
+
+// The inverse partial-sum scratch after the exchange planes of a chunk.
+float2* part_ptr(const shear_system* s, int batch, int chunk) {
+    if (part_bytes(s, chunk) == 0) return nullptr;
+    return (float2*)((char*)s->ws + (size_t)batch * plane_bytes(s) + (size_t)chunk * s->K * plane_bytes(s));
 }
 
 int ensure_ws(shear_system* s, size_t bytes) {
@@ -571,8 +580,9 @@ int inverse_like(shear_system* s, const float* coeffs, float* x, int batch, void
             return shear::launch_rows_r2c(d, coeffs + (size_t)b0 * d.K * img, U, nb * d.K, true, st);
         });
         if (e != hipSuccess) return hip_fail(e, "row r2c launch");
-        e = timed(s, SHEAR_KERNEL_COLS_INV, st,
-                  [&] { return shear::launch_cols_inv(d, U, V + (size_t)b0 * pb, nb, filt, st); });
+        e = timed(s, SHEAR_KERNEL_COLS_INV, st, [&] {
+            return shear::launch_cols_inv(d, U, V + (size_t)b0 * pb, nb, filt, part_ptr(s, batch, chunk), st);
+        });
         if (e != hipSuccess) return hip_fail(e, "column pass launch");
     }
     hipError_t e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
@@ -909,8 +919,9 @@ int shear_denoise(shear_system* s, const float* x, float* y, int batch, const fl
         });
         if (e != hipSuccess) return hip_fail(e, "row threshold launch");
         // the images of this chunk no longer need their row spectra: the sums replace them
-        e = timed(s, SHEAR_KERNEL_COLS_INV, st,
-                  [&] { return shear::launch_cols_inv(d, T, A + (size_t)b0 * pb, nb, s->filt_inv, st); });
+        e = timed(s, SHEAR_KERNEL_COLS_INV, st, [&] {
+            return shear::launch_cols_inv(d, T, A + (size_t)b0 * pb, nb, s->filt_inv, part_ptr(s, batch, chunk), st);
+        });
         if (e != hipSuccess) return hip_fail(e, "column pass launch");
     }
     e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st, [&] { return shear::launch_rows_c2r(d, A, y, batch, 1.0f, false, st); });
@@ -946,8 +957,9 @@ hipError_t enqueue_inpaint(shear_system* s, const float* fm, const float* mask, 
                 return shear::launch_rows_thresh(d, T, nb * d.K, thr + (size_t)b0 * d.K, nullptr, st);
             });
             if (e != hipSuccess) return e;
-            e = timed(s, SHEAR_KERNEL_COLS_INV, st,
-                      [&] { return shear::launch_cols_inv(d, T, A + (size_t)b0 * pb, nb, s->filt_inv, st); });
+            e = timed(s, SHEAR_KERNEL_COLS_INV, st, [&] {
+                return shear::launch_cols_inv(d, T, A + (size_t)b0 * pb, nb, s->filt_inv, part_ptr(s, batch, chunk), st);
+            });
             if (e != hipSuccess) return e;
         }
         e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
@@ -1010,23 +1022,38 @@ int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, flo
     return SHEAR_OK;
 }
 
-int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv) {
+int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv) {
     if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
     const int L = s->cols / 2;
     for (int pw : {pw_fwd, pw_inv}) {
         if (pw != 0 && pw != 8 && pw != 16) return fail(SHEAR_E_INVALID, "panel width must be 0, 8 or 16");
         if (pw == 16 && L < 16) return fail(SHEAR_E_INVALID, "panel width 16 needs cols >= 32");
     }
+    for (int kg : {kg_fwd, kg_inv})
+        if (kg < 0 || kg > s->K) return fail(SHEAR_E_INVALID, "filter groups must be in [0, K]");
     if (pw_fwd) s->plan.pw_fwd = pw_fwd;
     if (pw_inv) s->plan.pw_inv = pw_inv;
+    if (kg_fwd) s->plan.kg_fwd = kg_fwd;
+    if (kg_inv) s->plan.kg_inv = kg_inv;
+    drop_graph(s);  // a captured inpainting sequence holds the old schedule and workspace layout
     return SHEAR_OK;
 }
 
-int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv) {
+int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv) {
     int rc = check_call(s, s, s, batch);
     if (rc != SHEAR_OK) return rc;
+    std::vector<int> pws = {8};
+    if (s->cols / 2 >= 16) pws.insert(pws.begin(), 16);
+    std::vector<int> kgs;
+    for (int kg : {1, 2, 4, 8})
+        if (kg <= s->K) kgs.push_back(kg);
+    // the workspace and chunk of the largest filter split (its partial sums need the most room)
+    const shear::DevPlan saved = s->plan;
+    s->plan.kg_inv = kgs.back();
     int chunk = 0;
-    if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
+    rc = prepare_ws(s, batch, chunk);
+    s->plan = saved;
+    if (rc != SHEAR_OK) return rc;
     drop_graph(s);  // a captured inpainting sequence holds the old schedule
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
@@ -1036,44 +1063,53 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv) {
     const size_t pb = plane_bytes(s) / sizeof(float2);
     float2* A = (float2*)s->ws;
     float2* T = A + (size_t)batch * pb;
+    float2* part = T + (size_t)chunk * s->K * pb;
     const float scale = (float)(1.0 / ((double)s->rows * s->cols));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
         return hip_fail(e, "hipEventCreate");
     }
-    std::vector<int> cand = {8};
-    if (s->cols / 2 >= 16) cand.insert(cand.begin(), 16);
     constexpr int kReps = 3;
     for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-        float best = 0.0f;
-        int pick = cand[0];
-        for (int pw : cand) {
-            shear::DevPlan d = s->plan;
-            (dir == 0 ? d.pw_fwd : d.pw_inv) = pw;
-            auto launch = [&] {
-                return dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
-                                : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, nullptr);
-            };
-            if ((e = launch()) != hipSuccess) break;  // warm-up
-            if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) break;
-            for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch();
-            if (e != hipSuccess) break;
-            if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
-            float ms = 0.0f;
-            if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-            if (pw == cand[0] || ms < best) {
-                best = ms;
-                pick = pw;
+        float best = -1.0f;
+        int pick_pw = pws[0], pick_kg = 1;
+        for (int pw : pws) {
+            for (int kg : kgs) {
+                shear::DevPlan d = s->plan;
+                (dir == 0 ? d.pw_fwd : d.pw_inv) = pw;
+                (dir == 0 ? d.kg_fwd : d.kg_inv) = kg;
+                auto launch = [&] {
+                    return dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
+                                    : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, part, nullptr);
+                };
+                if ((e = launch()) != hipSuccess) break;  // warm-up
+                if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) break;
+                for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch();
+                if (e != hipSuccess) break;
+                if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
+                float ms = 0.0f;
+                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
+                if (best < 0.0f || ms < best) {
+                    best = ms;
+                    pick_pw = pw;
+                    pick_kg = kg;
+                }
             }
+            if (e != hipSuccess) break;
         }
-        if (e == hipSuccess) (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick;
+        if (e == hipSuccess) {
+            (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick_pw;
+            (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = pick_kg;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "autotune launch");
     if (pw_fwd) *pw_fwd = s->plan.pw_fwd;
     if (pw_inv) *pw_inv = s->plan.pw_inv;
+    if (kg_fwd) *kg_fwd = s->plan.kg_fwd;
+    if (kg_inv) *kg_inv = s->plan.kg_inv;
     return SHEAR_OK;
 }
 

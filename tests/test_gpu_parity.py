@@ -384,31 +384,46 @@ def test_path_profile_kinds(cfg1, gpu):
 # ---------------------------------------------------------------- column-pass schedules and the autotuner
 
 
-@pytest.mark.parametrize("N,M,J,B", [(256, 256, 3, 4), (1024, 1024, 4, 2), (512, 128, 2, 3)])
+@pytest.mark.parametrize("N,M,J,B", [(256, 256, 3, 4), (1024, 1024, 4, 2), (512, 128, 2, 3), (512, 512, 4, 1)])
 def test_schedules_agree_and_autotune(gpu, lib, N, M, J, B):
-    """Every column-pass schedule transforms each column with the same operations: the forward is
-    bitwise identical, the inverse agrees to rounding; the autotuner keeps one of them."""
+    """Every column-pass schedule (panel width, filter groups) transforms each column and filter with the
+    same operations: the forward is bitwise identical; the inverse sums the filters group by group, so it
+    agrees to rounding; the autotuner keeps one of them."""
     from paper_2006_04591_amd import ShearletSystem
 
     _say(f"case: schedules {N}x{M} J={J} B={B}")
+    ref = OF.build_system(N, M, J)
     with ShearletSystem.build(N, M, J) as s:
-        x = _to(synth.cartoon_batch(B, N, M, config=8, sigma=5.0), gpu)
+        xh = synth.cartoon_batch(B, N, M, config=8, sigma=5.0)
+        x = _to(xh, gpu)
         res = {}
         for pw in (16, 8):
-            s.set_schedule(pw, pw)
-            c = s.forward(x)
-            res[pw] = (c, s.inverse(c))
+            for kg in (1, 3, 8):
+                s.set_schedule(pw, pw, kg, kg)
+                c = s.forward(x)
+                res[(pw, kg)] = (c, s.inverse(c), s.adjoint(c))
         torch.cuda.synchronize()
-        assert torch.equal(res[16][0], res[8][0])
-        assert _rel(res[8][1].cpu().numpy(), res[16][1].cpu().numpy()) <= 1e-6
-        assert _rel(res[16][1].cpu().numpy(), x.cpu().numpy()) <= TOL
-        pf, pi = s.autotune(B)
-        assert pf in (8, 16) and pi in (8, 16)
+        c0, y0, a0 = res[(16, 1)]
+        for key, (c, y, a) in res.items():
+            assert torch.equal(c, c0), key
+            assert _rel(y.cpu().numpy(), y0.cpu().numpy()) <= 1e-6, key
+            assert _rel(a.cpu().numpy(), a0.cpu().numpy()) <= 1e-6, key
+        # the split inverse against the oracle (one image)
+        yk = res[(8, 8)][1][0].double().cpu().numpy()
+        c_in = res[(8, 8)][0][0].double().cpu().numpy()
+        assert _rel(yk, OT.inverse_plain(c_in, ref.spectra, ref.W)) <= TOL
+        assert _rel(y0.cpu().numpy(), xh) <= TOL
+        pf, pi, kf, ki = s.autotune(B)
+        assert pf in (8, 16) and pi in (8, 16) and 1 <= kf <= 8 and 1 <= ki <= 8
         c = s.forward(x)
+        y = s.inverse(c)
         torch.cuda.synchronize()
-        assert torch.equal(c, res[pf][0])
+        assert torch.equal(c, c0)
+        assert _rel(y.cpu().numpy(), y0.cpu().numpy()) <= 1e-6
         with pytest.raises(Exception):
             s.set_schedule(12, 0)
+        with pytest.raises(Exception):
+            s.set_schedule(0, 0, ref.K + 1, 0)
 
 
 def test_schedule_narrow_columns(gpu, lib):
@@ -419,4 +434,4 @@ def test_schedule_narrow_columns(gpu, lib):
     with ShearletSystem.from_spectra(S) as s:
         with pytest.raises(ShearError):
             s.set_schedule(16, 0)  # 8 packed columns: one panel of 8
-        assert s.autotune(2) == (8, 8)
+        assert s.autotune(2)[:2] == (8, 8)
