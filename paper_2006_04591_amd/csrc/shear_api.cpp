@@ -1185,6 +1185,8 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     off = al256(off + pix * 64);
     const size_t o_dh1 = off;
     off = al256(off + pix * 64);
+    const size_t o_z = off;
+    off = al256(off + pix * cpo * 2);
     const size_t o_t3 = off;
     off = al256(off + (size_t)32 * 9 * cpo * 2);
     const size_t o_t2 = off;
@@ -1199,6 +1201,7 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     unsigned short* dO = (unsigned short*)(w + o_do);
     unsigned short* dh2 = (unsigned short*)(w + o_dh2);
     unsigned short* dh1 = (unsigned short*)(w + o_dh1);
+    unsigned short* zp = (unsigned short*)(w + o_z);
     unsigned short* t3 = (unsigned short*)(w + o_t3);
     unsigned short* t2 = (unsigned short*)(w + o_t2);
     float* part = (float*)(w + o_part);
@@ -1211,13 +1214,14 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     hipError_t e;
     if ((e = shear::launch_zero_u32((unsigned*)loss, 1, st)) != hipSuccess) return hip_fail(e, "loss reset");
     if ((e = shear::launch_inv_scale(sigma, s->rms_dev, scale, batch, K, st)) != hipSuccess) return hip_fail(e, "scale");
+    if ((e = shear::launch_pack_z(c_noisy, scale, zp, K, N, M, batch, st)) != hipSuccess) return hip_fail(e, "z packing");
     // forward: h1, h2 (as in inference), then the loss epilogue of the last layer
     shear::ConvArgs a{};
     a.N = N;
     a.M = M;
     a.scale = scale;
     a.lowpass = K - 1;
-    a.in = c_noisy;
+    a.in = zp;
     a.W = (const unsigned short*)(pk + L.w1);
     a.bias = (const float*)(pk + L.b1);
     a.out_bf = h1;
@@ -1247,7 +1251,6 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     g.N = N;
     g.M = M;
     g.part = part;
-    g.scale = scale;
     g.dy = dO;
     g.dy_ch = cpo;
     g.xb = h2;
@@ -1277,9 +1280,7 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     if ((e = shear::launch_conv(4, K, bd, batch, st)) != hipSuccess) return hip_fail(e, "dh1");
     g.dy = dh1;
     g.dy_ch = 32;
-    g.xf = c_noisy;
-    g.xb = nullptr;
-    g.cin = K;
+    g.xb = zp;
     if ((e = shear::launch_wgrad(0, K, g, G, st)) != hipSuccess) return hip_fail(e, "dW1");
     if ((e = shear::launch_wgrad_reduce(part, grads + pW1, grads + pb1, G, 32, K, 32, cpo, st)) != hipSuccess)
         return hip_fail(e, "dW1 reduce");
@@ -1302,24 +1303,27 @@ int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, floa
         return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 32 == 0");
     const int K = s->K, N = s->rows, M = s->cols;
     const size_t act = (size_t)batch * N * M * 32 * 2;  // one bfloat16 activation tensor
+    const size_t zb = (size_t)batch * N * M * shear::shrink_cinp(K) * 2;
     const size_t sc = ((size_t)batch * K * sizeof(float) + 255) & ~(size_t)255;
-    if ((rc = ensure_ws2(s, sc + 2 * act)) != SHEAR_OK) return rc;
+    if ((rc = ensure_ws2(s, sc + 2 * act + zb)) != SHEAR_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     char* w = (char*)s->ws2;
     float* scale = (float*)w;
     void* h1 = w + sc;
     void* h2 = w + sc + act;
+    unsigned short* z = (unsigned short*)(w + sc + 2 * act);
     const shear::ShrinkLayout L = shear::shrink_layout(K);
     const char* p = (const char*)packed;
     hipError_t e = shear::launch_inv_scale(sigma, s->rms_dev, scale, batch, K, st);
     if (e != hipSuccess) return hip_fail(e, "scale launch");
+    if ((e = shear::launch_pack_z(coeffs, scale, z, K, N, M, batch, st)) != hipSuccess) return hip_fail(e, "z packing");
     shear::ConvArgs a{};
     a.N = N;
     a.M = M;
     a.scale = scale;
     a.lowpass = K - 1;
-    // layer 1: coefficients -> h1
-    a.in = coeffs;
+    // layer 1: z -> h1
+    a.in = z;
     a.W = (const unsigned short*)(p + L.w1);
     a.bias = (const float*)(p + L.b1);
     a.out_bf = h1;

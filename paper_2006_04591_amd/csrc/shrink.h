@@ -7,12 +7,13 @@
 
 namespace shear {
 
-// One 3x3 layer launch. Layer 0 reads FP32 channel-first coefficients (in,
-// scaled by scale[b*cin + c]); layers 1 and 2 read bfloat16 channel-last
-// activations [b][y][x][32]. Layers 0 and 1 write relu(conv + bias) as
-// bfloat16 channel-last activations (out_bf); layer 2 writes the shrunk FP32
-// coefficients out_f (coef kept where |coef * scale| >= softplus(conv + bias),
-// plane `lowpass` kept whole) and, if non-null, the thresholds tau.
+// One 3x3 layer launch. Every layer reads bfloat16 channel-last input: the
+// packed z [b][y][x][shrink_cinp(K)] (launch_pack_z) for layer 0, hidden
+// activations [b][y][x][32] for layers 1 and 2. Layers 0 and 1 write
+// relu(conv + bias) as bfloat16 channel-last activations (out_bf); layer 2
+// writes the shrunk FP32 coefficients out_f (coef kept where
+// |coef * scale| >= softplus(conv + bias), plane `lowpass` kept whole) and,
+// if non-null, the thresholds tau.
 struct ConvArgs {
     const void* in;
     const unsigned short* W;  // packed bfloat16 weights [coutp][9][cinp]
@@ -32,16 +33,14 @@ struct ConvArgs {
     float loss_scale, temperature;
 };
 
-// Weight-gradient launch: dy bf16 channel-last with dy_ch channels; input x either FP32 channel-first
-// coefficients (times scale, layer 0) or bf16 channel-last activations; per-block partials to part.
+// Weight-gradient launch: dy bf16 channel-last with dy_ch channels; input x bf16 channel-last (the packed z
+// for layer 0, else a hidden activation); per-block partials to part.
 struct WgradArgs {
     const unsigned short* dy;
     int dy_ch;
-    const float* xf;
-    const float* scale;
     const unsigned short* xb;
     float* part;
-    int batch, N, M, cin;
+    int batch, N, M;
 };
 
 // Byte offsets of the packed parameter block of a K-filter network.
@@ -58,6 +57,9 @@ ShrinkLayout shrink_layout(int K);
 hipError_t launch_shrink_pack(int K, const float* W1, const float* b1, const float* W2, const float* b2,
                               const float* W3, const float* b3, void* packed, hipStream_t st);
 hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, int B, int K, hipStream_t st);
+// z = bf16(c x scale) as channel-last [b][y][x][shrink_cinp(K)], zero padded (M a multiple of 32)
+hipError_t launch_pack_z(const float* c, const float* scale, unsigned short* z, int K, int N, int M, int batch,
+                         hipStream_t st);
 // layer 0, 1, 2: inference layers; 3: last layer with the training epilogue; 4: backward data from 32
 // gradient channels; 5: backward data from shrink_cinp(K) gradient channels.
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st);

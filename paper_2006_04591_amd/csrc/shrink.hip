@@ -59,30 +59,41 @@ __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(
 // Stages the halo tile of one image: MODE 0 from FP32 channel-first coefficient
 // planes (times scale[c], the noise normalisation), else from bfloat16
 // channel-last activations with CINP channels.
-template <int CINP, int MODE>
+// Stages the halo tile of one image from bfloat16 channel-last activations with CINP channels.
+template <int CINP>
 __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int b, int y0, int x0) {
     constexpr int PIX = Pix<CINP>::value;
     const int N = a.N, M = a.M;
-    if constexpr (MODE == 0) {
-        const float* in = reinterpret_cast<const float*>(a.in);
-        for (int i = threadIdx.x; i < CINP * HH * HW; i += THREADS) {
-            const int xx = i % HW, r = i / HW, yy = r % HH, c = r / HH;
-            float v = 0.0f;
-            if (c < a.cin) {
-                const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-                v = in[(((size_t)b * a.cin + c) * N + y) * M + x] * a.scale[b * a.cin + c];
-            }
-            s[(yy * HW + xx) * PIX + c] = f2bf(v);
-        }
-    } else {
-        const uint4* in = reinterpret_cast<const uint4*>(a.in);
-        constexpr int CH = CINP / 8;  // 16-byte chunks per pixel
-        for (int i = threadIdx.x; i < HH * HW * CH; i += THREADS) {
-            const int ch = i % CH, p = i / CH, xx = p % HW, yy = p / HW;
-            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-            const uint4 v = in[(((size_t)b * N + y) * M + x) * CH + ch];
-            *reinterpret_cast<uint4*>(s + (yy * HW + xx) * PIX + ch * 8) = v;
-        }
+    const uint4* in = reinterpret_cast<const uint4*>(a.in);
+    constexpr int CH = CINP / 8;  // 16-byte chunks per pixel
+    for (int i = threadIdx.x; i < HH * HW * CH; i += THREADS) {
+        const int ch = i % CH, p = i / CH, xx = p % HW, yy = p / HW;
+        const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
+        const uint4 v = in[(((size_t)b * N + y) * M + x) * CH + ch];
+        *reinterpret_cast<uint4*>(s + (yy * HW + xx) * PIX + ch * 8) = v;
+    }
+}
+
+// z = bf16(coefficients x scale), channel-first FP32 -> channel-last bf16 [b][y][x][CINP] (zero padded):
+// one block per 32 pixels of one row, transposed through LDS.
+template <int CINP>
+__global__ __launch_bounds__(THREADS) void k_pack_z(const float* __restrict__ c, const float* __restrict__ scale,
+                                                 unsigned short* __restrict__ z, int K, int N, int M) {
+    constexpr int PITCH = CINP + 8;
+    __shared__ __attribute__((aligned(16))) unsigned short t[TW * PITCH];
+    const int xb = M / TW;
+    const int x0 = (blockIdx.x % xb) * TW, y = (blockIdx.x / xb) % N, b = blockIdx.x / (xb * N);
+    for (int i = threadIdx.x; i < CINP * TW; i += THREADS) {
+        const int px = i % TW, k = i / TW;
+        float v = 0.0f;
+        if (k < K) v = c[(((size_t)b * K + k) * N + y) * M + x0 + px] * scale[b * K + k];
+        t[px * PITCH + k] = f2bf(v);
+    }
+    __syncthreads();
+    uint4* out = reinterpret_cast<uint4*>(z + (((size_t)b * N + y) * M + x0) * CINP);
+    for (int i = threadIdx.x; i < TW * CINP / 8; i += THREADS) {
+        const int ch = i % (CINP / 8), px = i / (CINP / 8);
+        out[i] = *reinterpret_cast<const uint4*>(t + px * PITCH + ch * 8);
     }
 }
 
@@ -119,7 +130,7 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
     }
 }
 
-// MODE 0: z (FP32 coefficients x scale) -> relu -> bf16 activations; MODE 1: activations -> relu -> activations;
+// MODE 1: bf16 activations (or the packed z) -> relu -> bf16 activations;
 // MODE 2: activations -> o + b -> tau = softplus -> shrink of the coefficients;
 // MODE 3 (training, last layer): o -> smooth-gate loss (summed into *loss) and its gradient d o, stored as
 //   bf16 channel-last planes [b][y][x][OUTC] (zero beyond K and on the low-pass plane);
@@ -134,33 +145,46 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     const int tx = a.M / TW, ty = a.N / TH;
     const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, b = blockIdx.x / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
-    stage<CINP, MODE>(a, s_in, b, y0, x0);
+    stage<CINP>(a, s_in, b, y0, x0);
     __syncthreads();
     f32x4 acc[4][NT];
     mma<CINP, COUTP>(a, s_in, acc);
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lm = 4 * (l / 16);
     if constexpr (MODE == 2) {
-        const float* c = a.coef;
+        // per group of 16 channels: o = acc + bias to LDS ([16][TH][TW] FP32), then row-contiguous
+        // passes over the coefficients: tau = softplus(o), keep |c scale| >= tau
+        float* so = reinterpret_cast<float*>(s_out);
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt) {
-            const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
+        for (int nt = 0; nt < NT; ++nt) {
+            const int k = nt * 16 + lr;
+            const float bias = a.bias[k];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const int k = nt * 16 + lr;
-                if (k >= a.cout) continue;
-                const size_t off = (((size_t)b * a.cout + k) * a.N + y) * a.M + x;
-                const float4 cv = *reinterpret_cast<const float4*>(c + off);
-                const float sc = a.scale[b * a.cout + k], bias = a.bias[k];
-                float t[4], v[4] = {cv.x, cv.y, cv.z, cv.w}, o[4];
+            for (int mt = 0; mt < 4; ++mt) {
+                const int p0 = (2 * w + mt / 2) * TW + (mt % 2) * 16 + lm;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    t[i] = (k == a.lowpass) ? 0.0f : softplusf(acc[mt][nt][i] + bias);
-                    o[i] = (fabsf(v[i] * sc) >= t[i]) ? v[i] : 0.0f;
+                for (int i = 0; i < 4; ++i) so[lr * (TH * TW) + p0 + i] = acc[mt][nt][i] + bias;
+            }
+            __syncthreads();
+            for (int i = threadIdx.x; i < 16 * TH * (TW / 4); i += THREADS) {
+                const int q = i % (TW / 4), row = (i / (TW / 4)) % TH, kc = i / (TH * (TW / 4));
+                const int kk = nt * 16 + kc;
+                if (kk >= a.cout) continue;
+                const size_t off = (((size_t)b * a.cout + kk) * a.N + y0 + row) * a.M + x0 + 4 * q;
+                const float4 cv = *reinterpret_cast<const float4*>(a.coef + off);
+                const float4 ov = *reinterpret_cast<const float4*>(so + kc * (TH * TW) + row * TW + 4 * q);
+                const float sc = a.scale[b * a.cout + kk];
+                const float v[4] = {cv.x, cv.y, cv.z, cv.w}, o[4] = {ov.x, ov.y, ov.z, ov.w};
+                float t[4], r[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    t[j] = (kk == a.lowpass) ? 0.0f : softplusf(o[j]);
+                    r[j] = (fabsf(v[j] * sc) >= t[j]) ? v[j] : 0.0f;
                 }
-                *reinterpret_cast<float4*>(a.out_f + off) = make_float4(o[0], o[1], o[2], o[3]);
+                *reinterpret_cast<float4*>(a.out_f + off) = make_float4(r[0], r[1], r[2], r[3]);
                 if (a.tau) *reinterpret_cast<float4*>(a.tau + off) = make_float4(t[0], t[1], t[2], t[3]);
             }
+            __syncthreads();
         }
     } else {
         // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel
@@ -229,8 +253,8 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
 // M = output channels, N = (tap, input channel), K = pixels (one 32-pixel tile row per step).
 // A block loops over pixel tiles (stride gridDim.x) and writes its partial sums, and the bias
 // gradient sum_p dy[co](p), to part[blockIdx.x]; k_wgrad_reduce adds the partials in block order.
-// INMODE 0: x = bf16(coefficients x scale) (FP32 channel-first in); 1: bf16 channel-last activations.
-template <int CINP, int COUTP, int INMODE>
+// x: bf16 channel-last with CINP channels (the packed z, or a hidden activation).
+template <int CINP, int COUTP>
 __global__ __launch_bounds__(THREADS) void k_wgrad(WgradArgs a) {
     constexpr int MT = COUTP / 16, NTT = 9 * CINP / 16, TT = MT * NTT, TPW = (TT + 3) / 4;
     extern __shared__ unsigned short smem[];
@@ -257,14 +281,7 @@ __global__ __launch_bounds__(THREADS) void k_wgrad(WgradArgs a) {
         for (int i = threadIdx.x; i < CINP * HH * HW; i += THREADS) {
             const int xx = i % HW, r = i / HW, yy = r % HH, ci = r / HH;
             const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-            unsigned short v = 0;
-            if constexpr (INMODE == 0) {
-                if (ci < a.cin)
-                    v = f2bf(a.xf[(((size_t)b * a.cin + ci) * N + y) * M + x] * a.scale[b * a.cin + ci]);
-            } else {
-                v = a.xb[(((size_t)b * N + y) * M + x) * CINP + ci];
-            }
-            s_x[i] = v;
+            s_x[i] = a.xb[(((size_t)b * N + y) * M + x) * CINP + ci];
         }
         __syncthreads();
         if (threadIdx.x < COUTP) {
@@ -390,15 +407,15 @@ hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int CINP, int COUTP, int INMODE>
+template <int CINP, int COUTP>
 hipError_t wgrad_t(const WgradArgs& a, int blocks, hipStream_t st) {
-    const void* fn = reinterpret_cast<const void*>(&k_wgrad<CINP, COUTP, INMODE>);
+    const void* fn = reinterpret_cast<const void*>(&k_wgrad<CINP, COUTP>);
     const size_t lds = ((size_t)COUTP * TH * TW + (size_t)CINP * HH * HW) * 2;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((k_wgrad<CINP, COUTP, INMODE>), dim3((unsigned)blocks), dim3(THREADS), lds, st, a);
+    hipLaunchKernelGGL((k_wgrad<CINP, COUTP>), dim3((unsigned)blocks), dim3(THREADS), lds, st, a);
     return hipGetLastError();
 }
 
@@ -450,7 +467,7 @@ hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, in
 }
 
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st) {
-    if (layer == 0) return shrink_cinp(K) == 32 ? conv_t<32, 32, 0>(a, batch, st) : conv_t<64, 32, 0>(a, batch, st);
+    if (layer == 0) return shrink_cinp(K) == 32 ? conv_t<32, 32, 1>(a, batch, st) : conv_t<64, 32, 1>(a, batch, st);
     if (layer == 1) return conv_t<32, 32, 1>(a, batch, st);
     if (layer == 3) {  // training: last layer with the loss epilogue, gradient planes of shrink_cinp(K) channels
         if (shrink_cinp(K) == 32) {
@@ -482,13 +499,13 @@ hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream
 namespace shear {
 
 hipError_t launch_wgrad(int layer, int K, const WgradArgs& a, int blocks, hipStream_t st) {
-    if (layer == 0) return shrink_cinp(K) == 32 ? wgrad_t<32, 32, 0>(a, blocks, st) : wgrad_t<64, 32, 0>(a, blocks, st);
-    if (layer == 1) return wgrad_t<32, 32, 1>(a, blocks, st);
+    if (layer == 0) return shrink_cinp(K) == 32 ? wgrad_t<32, 32>(a, blocks, st) : wgrad_t<64, 32>(a, blocks, st);
+    if (layer == 1) return wgrad_t<32, 32>(a, blocks, st);
     switch (shrink_coutp(K)) {
-        case 16: return wgrad_t<32, 16, 1>(a, blocks, st);
-        case 32: return wgrad_t<32, 32, 1>(a, blocks, st);
-        case 48: return wgrad_t<32, 48, 1>(a, blocks, st);
-        case 64: return wgrad_t<32, 64, 1>(a, blocks, st);
+        case 16: return wgrad_t<32, 16>(a, blocks, st);
+        case 32: return wgrad_t<32, 32>(a, blocks, st);
+        case 48: return wgrad_t<32, 48>(a, blocks, st);
+        case 64: return wgrad_t<32, 64>(a, blocks, st);
     }
     return hipErrorInvalidValue;
 }
@@ -514,6 +531,20 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, floa
     const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
     hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, g, m, v, n, lr, b1, b2, eps, c1,
                        c2);
+    return hipGetLastError();
+}
+
+}  // namespace shear
+
+namespace shear {
+
+hipError_t launch_pack_z(const float* c, const float* scale, unsigned short* z, int K, int N, int M, int batch,
+                         hipStream_t st) {
+    const dim3 grid((unsigned)((size_t)batch * N * (M / TW)));
+    if (shrink_cinp(K) == 32)
+        hipLaunchKernelGGL(k_pack_z<32>, grid, dim3(THREADS), 0, st, c, scale, z, K, N, M);
+    else
+        hipLaunchKernelGGL(k_pack_z<64>, grid, dim3(THREADS), 0, st, c, scale, z, K, N, M);
     return hipGetLastError();
 }
 
