@@ -419,8 +419,8 @@ def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_writ
     fw = copy_factor(cal_write_csv, "WRITE_SIZE")
     fetch = per_kernel(fetch_csv, "FETCH_SIZE")
     write = per_kernel(write_csv, "WRITE_SIZE")
-    kinds = {"k_rows_r2c<512, 0>": "rows_r2c_images", "k_cols_fwd<": "cols_fwd", "k_rows_c2r<512, 1>": "rows_c2r_coeffs",
-             "k_rows_r2c<512, 1>": "rows_r2c_coeffs", "k_cols_inv<": "cols_inv", "k_rows_c2r<512, 0>": "rows_c2r_images"}
+    kinds = {"k_rows_r2c<512, 0": "rows_r2c_images", "k_cols_fwd<": "cols_fwd", "k_rows_c2r<512, 1": "rows_c2r_coeffs",
+             "k_rows_r2c<512, 1": "rows_r2c_coeffs", "k_cols_inv<": "cols_inv", "k_rows_c2r<512, 0": "rows_c2r_images"}
     out = {}
     for name in fetch:
         kind = next((v for k, v in kinds.items() if k in name), None)

@@ -256,7 +256,15 @@ struct Pts {
     static constexpr int value = (L >= 1024) ? 16 : (L == 256 ? 16 : 8);
 };
 
-constexpr int RB = 16;  // rows per block in the standalone row passes
+constexpr int RB = 16;       // rows per block in the standalone row passes over images
+constexpr int RB_COEF = 32;  // ... over coefficient planes (when the plane has that many rows)
+
+// rows per block of the coefficient row passes: RB_COEF, or fewer where that would exceed 1024 threads
+template <int M>
+constexpr int coef_rows() {
+    constexpr int T = (M / 2) / Pts<M / 2>::value;
+    return (RB_COEF * T <= 1024) ? RB_COEF : 1024 / T;
+}
 
 template <bool REAL>
 __device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, float2 a) {
@@ -493,17 +501,18 @@ __device__ __forceinline__ void col_inv_finish(float2 (&acc)[P], int col0, float
 // ---------------------------------------------------------------- standalone kernels
 
 // TAG only separates launch roles into distinct symbols (0: images, 1: coefficient planes)
-template <int M, int TAG>
-__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(const float* __restrict__ in,
+template <int M, int TAG, int ROWS>
+__global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(const float* __restrict__ in,
                                                                              float2* __restrict__ out, int N,
                                                                              const float2* __restrict__ twL,
                                                                              const float2* __restrict__ twM) {
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
-    const int nrb = N / RB;
+    const int nrb = N / ROWS;
     const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * RB;
-    row_r2c_tile<M, Pts<L>::value, RB>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM, (int)threadIdx.x);
+    const int row0 = (blockIdx.x % nrb) * ROWS;
+    row_r2c_tile<M, Pts<L>::value, ROWS>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM,
+                                         (int)threadIdx.x);
 }
 
 // Row stage of one inpainting iteration (Algorithm 3): the rows of
@@ -533,18 +542,18 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c_mix
         out + (size_t)plane * L * N, N, row0, lds, twL, twM, (int)threadIdx.x);
 }
 
-template <int M, int TAG>
-__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(const float2* __restrict__ in,
+template <int M, int TAG, int ROWS>
+__global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(const float2* __restrict__ in,
                                                                              float* __restrict__ out, int N,
                                                                              const float2* __restrict__ twL,
                                                                              const float2* __restrict__ twM,
                                                                              float scale) {
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
-    const int nrb = N / RB;
+    const int nrb = N / ROWS;
     const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * RB;
-    row_c2r_tile<M, Pts<L>::value, RB>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL, twM,
+    const int row0 = (blockIdx.x % nrb) * ROWS;
+    row_c2r_tile<M, Pts<L>::value, ROWS>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL, twM,
                                        scale, (int)threadIdx.x);
 }
 
@@ -632,19 +641,19 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
     }
 }
 
-// planes[p] for p < gridDim.x / (N / RB): threshold thr[p], kept counts kept[p]
-template <int M>
-__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_thresh(float2* __restrict__ planes, int N,
+// planes[p] for p < gridDim.x / (N / ROWS): threshold thr[p], kept counts kept[p]
+template <int M, int ROWS>
+__global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_thresh(float2* __restrict__ planes, int N,
                                                                               const float* __restrict__ thr,
                                                                               unsigned* __restrict__ kept,
                                                                               const float2* __restrict__ twL,
                                                                               const float2* __restrict__ twM) {
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
-    const int nrb = N / RB;
+    const int nrb = N / ROWS;
     const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * RB;
-    row_thresh_tile<M, Pts<L>::value, RB>(planes + (size_t)plane * L * N, N, row0, lds, twL, twM, thr[plane],
+    const int row0 = (blockIdx.x % nrb) * ROWS;
+    row_thresh_tile<M, Pts<L>::value, ROWS>(planes + (size_t)plane * L * N, N, row0, lds, twL, twM, thr[plane],
                                           kept ? kept + plane : nullptr, (int)threadIdx.x);
 }
 
@@ -1094,27 +1103,42 @@ hipError_t set_lds(F* fn, size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <int M, int TAG>
-hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
+// rows per block: RB_COEF (capped by coef_rows) for the r2c pass over coefficient planes with at least that
+// many rows, else RB
+template <int M, int TAG, int ROWS>
+hipError_t rows_r2c_rt(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
-    hipError_t e = set_lds(k_rows_r2c<M, TAG>, lds);
+    const size_t lds = (size_t)ROWS * RowPitch<L, P>::value * sizeof(float2);
+    hipError_t e = set_lds(k_rows_r2c<M, TAG, ROWS>, lds);
     if (e != hipSuccess) return e;
-    const size_t blocks = (size_t)planes * (d.N / RB);
-    hipLaunchKernelGGL((k_rows_r2c<M, TAG>), dim3((unsigned)blocks), dim3(RB * T), lds, st, in, out, d.N, d.twL, d.twM);
+    const size_t blocks = (size_t)planes * (d.N / ROWS);
+    hipLaunchKernelGGL((k_rows_r2c<M, TAG, ROWS>), dim3((unsigned)blocks), dim3(ROWS * T), lds, st, in, out, d.N, d.twL,
+                       d.twM);
     return hipGetLastError();
 }
 
 template <int M, int TAG>
-hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
+hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
+    if (TAG == 1 && d.N >= coef_rows<M>()) return rows_r2c_rt<M, TAG, coef_rows<M>()>(d, in, out, planes, st);
+    return rows_r2c_rt<M, TAG, RB>(d, in, out, planes, st);
+}
+
+template <int M, int TAG, int ROWS>
+hipError_t rows_c2r_rt(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
-    hipError_t e = set_lds(k_rows_c2r<M, TAG>, lds);
+    const size_t lds = (size_t)ROWS * RowPitch<L, P>::value * sizeof(float2);
+    hipError_t e = set_lds(k_rows_c2r<M, TAG, ROWS>, lds);
     if (e != hipSuccess) return e;
-    const size_t blocks = (size_t)planes * (d.N / RB);
-    hipLaunchKernelGGL((k_rows_c2r<M, TAG>), dim3((unsigned)blocks), dim3(RB * T), lds, st, in, out, d.N, d.twL,
+    const size_t blocks = (size_t)planes * (d.N / ROWS);
+    hipLaunchKernelGGL((k_rows_c2r<M, TAG, ROWS>), dim3((unsigned)blocks), dim3(ROWS * T), lds, st, in, out, d.N, d.twL,
                        d.twM, scale);
     return hipGetLastError();
+}
+
+// (the c2r passes measured faster with 16-row tiles, the coefficient r2c pass with 32)
+template <int M, int TAG>
+hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
+    return rows_c2r_rt<M, TAG, RB>(d, in, out, planes, scale, st);
 }
 
 template <int M>
@@ -1130,17 +1154,24 @@ hipError_t rows_r2c_mix_t(const DevPlan& d, const float* fm, const float* mask, 
     return hipGetLastError();
 }
 
+template <int M, int ROWS>
+hipError_t rows_thresh_rt(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
+                          hipStream_t st) {
+    constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
+    const size_t lds = (size_t)ROWS * RowPitch<L, P>::value * sizeof(float2);
+    hipError_t e = set_lds(k_rows_thresh<M, ROWS>, lds);
+    if (e != hipSuccess) return e;
+    const size_t blocks = (size_t)nplanes * (d.N / ROWS);
+    hipLaunchKernelGGL((k_rows_thresh<M, ROWS>), dim3((unsigned)blocks), dim3(ROWS * T), lds, st, planes, d.N, thr, kept,
+                       d.twL, d.twM);
+    return hipGetLastError();
+}
+
 template <int M>
 hipError_t rows_thresh_t(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
                          hipStream_t st) {
-    constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
-    hipError_t e = set_lds(k_rows_thresh<M>, lds);
-    if (e != hipSuccess) return e;
-    const size_t blocks = (size_t)nplanes * (d.N / RB);
-    hipLaunchKernelGGL((k_rows_thresh<M>), dim3((unsigned)blocks), dim3(RB * T), lds, st, planes, d.N, thr, kept,
-                       d.twL, d.twM);
-    return hipGetLastError();
+    if (d.N >= coef_rows<M>()) return rows_thresh_rt<M, coef_rows<M>()>(d, planes, nplanes, thr, kept, st);
+    return rows_thresh_rt<M, RB>(d, planes, nplanes, thr, kept, st);
 }
 
 // filters per group for kg requested groups, and the groups that gives
