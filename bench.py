@@ -110,6 +110,35 @@ def traffic_from_profiles(kind: str, per_launch_units: float):
         return None
 
 
+def device_copy_gbs(mib: int = 512, reps: int = 5) -> float:
+    """Bytes read plus written per second by a device-to-device copy of `mib` MiB: the practical
+    bandwidth ceiling beside the 8 TB/s specification."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * n * 4 * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(x_host, min_seconds: float, max_images: int, workload: str = "fwdinv") -> dict:
     """The FP64 oracle (numpy, as it stands) on a bounded sample of the same workload:
     fwd+inv (or denoising) of the batch images in order (cycling), until min_seconds have elapsed."""
@@ -146,6 +175,8 @@ def cpu_baseline(x_host, min_seconds: float, max_images: int, workload: str = "f
         "value": units / dt,
         "unit": "Mpix·filters/s",
         "cores": 1,
+        "cpu": cpu_model(),
+        "host_cpus": os.cpu_count(),
         "kind": "oracle",
         "sample": f"numpy FP64 oracle, {dict(denoise='denoising', layer='forward+adjoint').get(workload, 'fwd+inv')} "
                   f"of {n} images of the {N}x{M}, {ref.K}-filter batch (cycling through the {B}), {dt:.1f} s; "
@@ -450,8 +481,8 @@ def main() -> int:
         return traffic_summary(a[0], a[1], a[2], a[3], int(a[4]))
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle baseline sample length (0 = skip)")
     ap.add_argument("--path", default="separate", choices=("pipeline", "separate", "persistent"),
                     help="execution path of the transform calls")
@@ -540,16 +571,16 @@ def main() -> int:
     log(f"bench: {args.warmup} warmup steps done")
 
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     shs.profile(True)
     torch.cuda.synchronize()
-    ev0.record(stream)
+    evs[0].record(stream)
     for i in range(args.steps):
         step()
-    ev1.record(stream)
+        evs[i + 1].record(stream)
     torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
+    ms_total = evs[0].elapsed_time(evs[-1])
+    per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     rec = shs.profile_read()
     shs.profile(False)
     shs.check()
@@ -638,6 +669,8 @@ def main() -> int:
         "system_build_s": build_s,
     }
     out["config"]["column_schedule"] = list(schedule)
+    out["ms_per_step_p10_p50_p90"] = [float(v) for v in np.percentile(per_step, [10, 50, 90])]
+    out["device_copy_GBs"] = device_copy_gbs()
     if denoise:
         out.update(quality)
         out["config"]["path"] = "separate (fused row threshold kernel)"
