@@ -166,7 +166,7 @@ int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, flo
  * W2 32x32x3x3, W3 Kx32x3x3 (FP32, natural order [out][in][dy][dx]), biases FP32.
  * The matrix-core kernels compute with bfloat16 operands (z, weights and the
  * hidden activations rounded to bfloat16) and FP32 accumulation. K <= 64,
- * rows % 8 == 0, cols % 32 == 0 (else SHEAR_E_SIZE). */
+ * rows % 8 == 0, cols % 128 == 0 (else SHEAR_E_SIZE). */
 
 /* Bytes of the packed (device) parameter block of a K-filter network. */
 int shear_shrink_params_bytes(int K, size_t* bytes);

@@ -1164,7 +1164,7 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     if (step < 1 || !(temperature > 0.0f) || !(lr >= 0.0f))
         return fail(SHEAR_E_INVALID, "step must be >= 1, temperature > 0 and lr >= 0");
     if (!shear::shrink_supported(s->K, s->rows, s->cols))
-        return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 32 == 0");
+        return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 128 == 0");
     const int K = s->K, N = s->rows, M = s->cols;
     const int cpo = shear::shrink_cinp(K), c3 = shear::shrink_coutp(K);
     const size_t pix = (size_t)batch * N * M;
@@ -1300,7 +1300,7 @@ int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, floa
     if (rc != SHEAR_OK) return rc;
     if (!sigma || !packed) return fail(SHEAR_E_INVALID, "sigma or parameter pointer is NULL");
     if (!shear::shrink_supported(s->K, s->rows, s->cols))
-        return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 32 == 0");
+        return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 128 == 0");
     const int K = s->K, N = s->rows, M = s->cols;
     const size_t act = (size_t)batch * N * M * 32 * 2;  // one bfloat16 activation tensor
     const size_t zb = (size_t)batch * N * M * shear::shrink_cinp(K) * 2;

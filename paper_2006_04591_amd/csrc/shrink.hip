@@ -75,23 +75,25 @@ __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int 
 }
 
 // z = bf16(coefficients x scale), channel-first FP32 -> channel-last bf16 [b][y][x][CINP] (zero padded):
-// one block per 32 pixels of one row, transposed through LDS.
+// one block per ZW pixels of one row (512-byte runs of each plane), transposed through LDS.
+constexpr int ZW = 128;
+
 template <int CINP>
 __global__ __launch_bounds__(THREADS) void k_pack_z(const float* __restrict__ c, const float* __restrict__ scale,
                                                  unsigned short* __restrict__ z, int K, int N, int M) {
     constexpr int PITCH = CINP + 8;
-    __shared__ __attribute__((aligned(16))) unsigned short t[TW * PITCH];
-    const int xb = M / TW;
-    const int x0 = (blockIdx.x % xb) * TW, y = (blockIdx.x / xb) % N, b = blockIdx.x / (xb * N);
-    for (int i = threadIdx.x; i < CINP * TW; i += THREADS) {
-        const int px = i % TW, k = i / TW;
+    __shared__ __attribute__((aligned(16))) unsigned short t[ZW * PITCH];
+    const int xb = M / ZW;
+    const int x0 = (blockIdx.x % xb) * ZW, y = (blockIdx.x / xb) % N, b = blockIdx.x / (xb * N);
+    for (int i = threadIdx.x; i < CINP * ZW; i += THREADS) {
+        const int px = i % ZW, k = i / ZW;
         float v = 0.0f;
         if (k < K) v = c[(((size_t)b * K + k) * N + y) * M + x0 + px] * scale[b * K + k];
         t[px * PITCH + k] = f2bf(v);
     }
     __syncthreads();
     uint4* out = reinterpret_cast<uint4*>(z + (((size_t)b * N + y) * M + x0) * CINP);
-    for (int i = threadIdx.x; i < TW * CINP / 8; i += THREADS) {
+    for (int i = threadIdx.x; i < ZW * CINP / 8; i += THREADS) {
         const int ch = i % (CINP / 8), px = i / (CINP / 8);
         out[i] = *reinterpret_cast<const uint4*>(t + px * PITCH + ch * 8);
     }
@@ -423,7 +425,7 @@ hipError_t wgrad_t(const WgradArgs& a, int blocks, hipStream_t st) {
 
 int shrink_cinp(int K) { return K <= 32 ? 32 : 64; }
 int shrink_coutp(int K) { return (K + 15) / 16 * 16; }
-bool shrink_supported(int K, int N, int M) { return K >= 1 && K <= 64 && N >= TH && M >= TW && N % TH == 0 && M % TW == 0; }
+bool shrink_supported(int K, int N, int M) { return K >= 1 && K <= 64 && N >= TH && N % TH == 0 && M % ZW == 0; }
 
 ShrinkLayout shrink_layout(int K) {
     ShrinkLayout L;
@@ -540,7 +542,8 @@ namespace shear {
 
 hipError_t launch_pack_z(const float* c, const float* scale, unsigned short* z, int K, int N, int M, int batch,
                          hipStream_t st) {
-    const dim3 grid((unsigned)((size_t)batch * N * (M / TW)));
+    if (M % ZW != 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((size_t)batch * N * (M / ZW)));
     if (shrink_cinp(K) == 32)
         hipLaunchKernelGGL(k_pack_z<32>, grid, dim3(THREADS), 0, st, c, scale, z, K, N, M);
     else

@@ -129,7 +129,7 @@ def test_shrink_errors(gpu):
     with ShearletSystem.from_spectra(S) as s:
         net = ShrinkNet(s, _params_dict(p))
         with pytest.raises(ShearError) as e:
-            net.apply(_to(np.zeros((1, 2, 16, 16)), gpu), 1.0)  # 16 columns: below one 32-column tile
+            net.apply(_to(np.zeros((1, 2, 16, 16)), gpu), 1.0)  # 16 columns: not a multiple of 128
         assert e.value.name == "SHEAR_E_SIZE"
         with pytest.raises(ValueError):
             ShrinkNet(s, {**_params_dict(p), "W1": np.zeros((32, 3, 3, 3))})
