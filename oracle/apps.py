@@ -123,6 +123,7 @@ def inpaint(f_masked: np.ndarray, mask: np.ndarray, spectra: np.ndarray, W: np.n
     f_inpainted = 0; for each delta of the schedule (``delta_schedule``: the paper's geometric decay)
       f_res = M (f_masked - f_inpainted)
       f_inpainted = SH^-1 T_{delta RMS} SH (f_res + f_inpainted).
+    ``deltas`` is (iterations,) scalars, or (iterations, K) per-filter thresholds used as given.
     """
     M = np.asarray(mask, dtype=np.float64)
     fm = np.asarray(f_masked, dtype=np.float64)
@@ -130,5 +131,6 @@ def inpaint(f_masked: np.ndarray, mask: np.ndarray, spectra: np.ndarray, W: np.n
     r = np.asarray(rms, dtype=np.float64)
     for delta in np.asarray(deltas, dtype=np.float64):
         f_res = M * (fm - f)
-        f = denoise(f_res + f, spectra, W, delta * r)
+        # a scalar delta is weighted by the filters' RMS; a row of K values is used as the thresholds
+        f = denoise(f_res + f, spectra, W, delta * r if np.ndim(delta) == 0 else delta)
     return f
