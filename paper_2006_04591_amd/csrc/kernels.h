@@ -31,18 +31,19 @@ inline size_t cols_inv_part_elems(const DevPlan& d, int nimg) {
 }
 
 // coeff_planes selects a separate kernel symbol for coefficient planes (same code).
-// Rows (real, row-major planes x N x M) -> packed row spectra, column-major
-// (planes x L x N): out[p][k][r] = sum_c in[p][r][c] e^{-2 pi i k c / M}, with
-// out[p][0][r] = X(0) + i X(M/2).
+// Rows (real, row-major planes x N x M) -> packed row spectra, planes of L x N
+// float2 in the panel layout of kernels.hip (panels of 8 columns, 16-row tiles
+// down each panel): element (r, k) = sum_c in[p][r][c] e^{-2 pi i k c / M},
+// with element (r, 0) = X(0) + i X(M/2).
 hipError_t launch_rows_r2c(const DevPlan& d, const float* in, float2* out, int planes, bool coeff_planes,
                            hipStream_t st);
 
-// Inverse of the above up to scale: packed column-major spectra -> real rows,
+// Inverse of the above up to scale: packed spectra (panel layout) -> real rows,
 // out = scale * (unnormalised length-M inverse DFT of the Hermitian rows).
 hipError_t launch_rows_c2r(const DevPlan& d, const float2* in, float* out, int planes, float scale, bool coeff_planes,
                            hipStream_t st);
 // Row stage of an inpainting iteration: rows of u = mask (fm - f) + f (planes x N x M each) -> packed
-// column-major spectra, as launch_rows_r2c.
+// spectra in the panel layout, as launch_rows_r2c.
 hipError_t launch_rows_r2c_mix(const DevPlan& d, const float* fm, const float* mask, const float* f, float2* out,
                                int planes, hipStream_t st);
 // Coefficient row stages with a hard threshold between them, in place on

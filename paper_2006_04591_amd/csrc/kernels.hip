@@ -7,7 +7,7 @@
 // A real row of M samples is transformed as M/2 complex samples plus a
 // post-twiddle; the real DC and Nyquist bins of each row spectrum share one
 // complex slot ("packed" column 0), so every intermediate plane is N x M/2
-// complex, stored column-major so column passes read whole columns.
+// complex, stored in panels of 8 columns made of 16-row tiles (xoff below).
 //
 // FFTs are Stockham autosort passes (radix 2/4/8/16 butterflies in
 // registers, LDS between passes). A thread of an FFT group of T = L/P threads
@@ -61,6 +61,17 @@ __device__ __forceinline__ void st_x(float2* p, float2 a) {
     } else {
         *p = a;
     }
+}
+
+// Layout of an intermediate N x L packed plane (N a multiple of 16, L of 8):
+// panels of 8 consecutive columns, each panel N x 8 float2 contiguous, made of
+// tiles of 16 rows x 8 columns (128 float2, column-major inside the tile, so 16
+// rows of one column are one 128-byte line), tile after tile down the panel.
+// A column pass reads or writes whole panels as contiguous runs, as with a
+// column-major plane; a row pass over 16 rows reads or writes one 1 KB run per
+// panel instead of one 128-byte line per column.
+__device__ __forceinline__ size_t xoff(int row, int col, int N) {
+    return (size_t)(col >> 3) * ((size_t)N << 3) + (size_t)(((row >> 4) << 7) | ((col & 7) << 4) | (row & 15));
 }
 
 // ---------------------------------------------------------------- butterflies
@@ -280,7 +291,7 @@ __device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, flo
 // (thread t of row r is threadIdx.x = t + (L/P) r). lds holds ROWS * (L + 1) float2.
 // The caller separates consecutive tiles that reuse lds with a barrier.
 
-// real rows -> packed spectra, column-major plane out[k * N + row]
+// real rows -> packed spectra, plane out in the panel layout (xoff)
 // per-row LDS pitch of the row tiles: FFT scratch footprint plus one slot, so
 // that column-wise accesses of consecutive rows fall on different banks
 template <int L, int P>
@@ -305,7 +316,6 @@ __device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __rest
     __syncthreads();
     const int r2 = tid % ROWS, kk = tid / ROWS;
     const float2* s2 = lds + r2 * PITCH;
-    float2* dst = out_plane + row0 + r2;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
         const int k = kk + T * i;
@@ -320,7 +330,7 @@ __device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __rest
             const float2 O = make_float2(D.y, -D.x);  // (Z - conj Zm) / (2i)
             X = cadd(E, cmul(twM[k], O));
         }
-        st_x<XS>(dst + (size_t)k * N, X);
+        st_x<XS>(out_plane + xoff(row0 + r2, k, N), X);
     }
 }
 
@@ -334,7 +344,7 @@ __device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane,
         twM, tid);
 }
 
-// packed column-major spectra -> real rows, out = scale * unnormalised inverse
+// packed spectra (panel layout) -> real rows, out = scale * unnormalised inverse
 template <int M, int P, int ROWS, bool XS = true>
 __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane, float* __restrict__ out_plane, int N,
                                              int row0, float2* lds, const float2* __restrict__ twL,
@@ -343,11 +353,10 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
     {
         const int r2 = tid % ROWS, kk = tid / ROWS;
         float2* s2 = lds + r2 * PITCH;
-        const float2* src = in_plane + row0 + r2;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int k = kk + T * i;
-            s2[k] = ld_x<XS>(src + (size_t)k * N);
+            s2[k] = ld_x<XS>(in_plane + xoff(row0 + r2, k, N));
         }
     }
     __syncthreads();
@@ -377,7 +386,7 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
 
 // ---------------------------------------------------------------- column panels
 // A panel is PW consecutive columns [col0, col0 + PW) of an N x L packed plane
-// stored column-major (element (row, col) at col * N + row), handled by
+// in the panel layout (element (row, col) at xoff(row, col, N)), handled by
 // PW * (N/P) threads: thread t of panel column c is threadIdx.x = t + (N/P) c.
 // lds holds PW FFT scratches of ColScratch<N, P> float2 plus the N-float2
 // mirror buffer used by packed column 0.
@@ -395,9 +404,8 @@ __device__ __forceinline__ void col_fwd_setup(const float2* __restrict__ a_img, 
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
     float2* smir = lds + PW * ColScratch<N, P>::value;
-    const float2* a = a_img + (size_t)col * N;
 #pragma unroll
-    for (int q = 0; q < P; ++q) xh[q] = cscale(a[t + T * q], scale);
+    for (int q = 0; q < P; ++q) xh[q] = cscale(a_img[xoff(t + T * q, col, N)], scale);
     fft<N, P, false>(xh, s, t, twN);
     if (col == 0) {
 #pragma unroll
@@ -430,9 +438,8 @@ __device__ __forceinline__ void col_fwd_emit(const float2 (&xh)[P], const void* 
         }
     }
     fft<N, P, true>(y, s, t, twN);
-    float2* o = out_plane + (size_t)col * N;
 #pragma unroll
-    for (int q = 0; q < P; ++q) st_x<XS>(o + t + T * q, y[q]);
+    for (int q = 0; q < P; ++q) st_x<XS>(out_plane + xoff(t + T * q, col, N), y[q]);
 }
 
 // The mirrored-term accumulator g of packed column 0 lives in the panel's
@@ -458,10 +465,9 @@ __device__ __forceinline__ void col_inv_accum(const float2* __restrict__ u_plane
     const int t = tid % T, c = tid / T;
     const int col = col0 + c;
     float2* s = lds + c * ColScratch<N, P>::value;
-    const float2* u = u_plane + (size_t)col * N;
     float2 x[P];
 #pragma unroll
-    for (int q = 0; q < P; ++q) x[q] = ld_x<XS>(u + t + T * q);
+    for (int q = 0; q < P; ++q) x[q] = ld_x<XS>(u_plane + xoff(t + T * q, col, N));
     fft<N, P, false>(x, s, t, twN);
     const size_t fstride = (size_t)(L + 1) * N;
     const size_t fbase = (size_t)k * fstride + (size_t)col * N;
@@ -493,9 +499,8 @@ __device__ __forceinline__ void col_inv_finish(float2 (&acc)[P], int col0, float
         }
     }
     fft<N, P, true>(acc, s, t, twN);
-    float2* o = v_img + (size_t)col * N;
 #pragma unroll
-    for (int q = 0; q < P; ++q) o[t + T * q] = acc[q];
+    for (int q = 0; q < P; ++q) v_img[xoff(t + T * q, col, N)] = acc[q];
 }
 
 // ---------------------------------------------------------------- standalone kernels
@@ -558,7 +563,7 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(c
 }
 
 // Forward row stage, hard threshold and inverse row stage of one tile of a
-// coefficient plane, in place on its packed column-major spectra: the rows
+// coefficient plane, in place on its packed (panel layout) spectra: the rows
 // become real coefficients c (as the forward transform writes them), every
 // coefficient with |c| < thr is set to zero, and the thresholded rows are
 // transformed back, so thresholded coefficients never leave the chip. The
@@ -571,11 +576,10 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
     const int r2 = tid % ROWS, kk = tid / ROWS;
     {
         float2* s2 = lds + r2 * PITCH;
-        const float2* src = plane + row0 + r2;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int k = kk + T * i;
-            s2[k] = ld_stream(src + (size_t)k * N);
+            s2[k] = ld_stream(plane + xoff(row0 + r2, k, N));
         }
     }
     __syncthreads();
@@ -614,7 +618,6 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
     __syncthreads();
     {
         const float2* s2 = lds + r2 * PITCH;
-        float2* dst = plane + row0 + r2;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
             const int k = kk + T * i;
@@ -629,7 +632,7 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
                 const float2 O = make_float2(D.y, -D.x);
                 X = cadd(E, cmul(twM[k], O));
             }
-            st_stream(dst + (size_t)k * N, X);
+            st_stream(plane + xoff(row0 + r2, k, N), X);
         }
     }
     if (kept != nullptr) {
