@@ -491,6 +491,9 @@ def main() -> int:
     ap.add_argument("--chunk-images", type=int, default=0,
                     help="images per chunk of the K-expanded intermediate (0 = whole batch)")
     ap.add_argument("--train-steps", type=int, default=1250, help="shrink: training steps (16 pairs each)")
+    ap.add_argument("--schedule", default="",
+                    help="fwdinv/denoise/layer: fixed column-pass schedule 'pw_fwd,pw_inv,kg_fwd,kg_inv' instead of "
+                         "the autotuner (counter runs use it so that one kernel variant runs)")
     ap.add_argument("--workload", default="fwdinv", choices=("fwdinv", "denoise", "layer", "inpaint", "shrink"),
                     help="fwdinv: shear_forward + shear_inverse (the headline); denoise: shear_denoise with the "
                          "paper's thresholds (Section 4.2); layer: the autograd layer's forward and backward at "
@@ -542,8 +545,16 @@ def main() -> int:
     c = torch.empty((B, K, N, M), dtype=torch.float32, device=dev)
     y = torch.empty((B, N, M), dtype=torch.float32, device=dev)
     shs.reserve(B)
-    schedule = shs.autotune(B)
-    log(f"bench: autotuned column-pass schedule (columns per block, fwd/inv): {schedule}")
+    if args.schedule:
+        schedule = tuple(int(v) for v in args.schedule.split(","))
+        if len(schedule) != 4:
+            print("bench.py: --schedule needs four integers pw_fwd,pw_inv,kg_fwd,kg_inv", file=sys.stderr)
+            return 2
+        shs.set_schedule(*schedule)
+        log(f"bench: fixed column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv): {schedule}")
+    else:
+        schedule = shs.autotune(B)
+        log(f"bench: autotuned column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv): {schedule}")
     # denoising workload: hard threshold 3 sigma RMS_k on every band, low-pass kept
     thr = torch.from_numpy(np.tile(shs.paper_thresholds(SIGMA, factors=[3.0] * J), (B, 1))).to(dev)
     if layer:
