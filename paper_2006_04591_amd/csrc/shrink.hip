@@ -56,9 +56,6 @@ constexpr size_t conv_lds_bytes() {
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// Stages the halo tile of one image: MODE 0 from FP32 channel-first coefficient
-// planes (times scale[c], the noise normalisation), else from bfloat16
-// channel-last activations with CINP channels.
 // Stages the halo tile of one image from bfloat16 channel-last activations with CINP channels.
 template <int CINP>
 __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int b, int y0, int x0) {
@@ -143,7 +140,6 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     constexpr int NT = COUTP / 16;
     extern __shared__ unsigned short smem[];
     unsigned short* s_in = smem;
-    unsigned short* s_out = smem + HH * HW * Pix<CINP>::value;
     const int tx = a.M / TW, ty = a.N / TH;
     const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, b = blockIdx.x / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
@@ -154,42 +150,35 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lm = 4 * (l / 16);
     if constexpr (MODE == 2) {
-        // per group of 16 channels: o = acc + bias to LDS ([16][TH][TW] FP32), then row-contiguous
-        // passes over the coefficients: tau = softplus(o), keep |c scale| >= tau
-        float* so = reinterpret_cast<float*>(s_out);
+        // o = acc + bias, tau = softplus(o) (0 on the low-pass plane), keep |c scale| >= tau. A lane
+        // holds 4 consecutive pixels of one channel, so it reads and writes the channel-first
+        // coefficient planes directly as 16-byte vectors.
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int k = nt * 16 + lr;
+            if (k >= a.cout) continue;
             const float bias = a.bias[k];
+            const float sc = a.scale[b * a.cout + k];
+            const bool lowpass = (k == a.lowpass);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const int p0 = (2 * w + mt / 2) * TW + (mt % 2) * 16 + lm;
-#pragma unroll
-                for (int i = 0; i < 4; ++i) so[lr * (TH * TW) + p0 + i] = acc[mt][nt][i] + bias;
-            }
-            __syncthreads();
-            for (int i = threadIdx.x; i < 16 * TH * (TW / 4); i += THREADS) {
-                const int q = i % (TW / 4), row = (i / (TW / 4)) % TH, kc = i / (TH * (TW / 4));
-                const int kk = nt * 16 + kc;
-                if (kk >= a.cout) continue;
-                const size_t off = (((size_t)b * a.cout + kk) * a.N + y0 + row) * a.M + x0 + 4 * q;
+                const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
+                const size_t off = (((size_t)b * a.cout + k) * a.N + y) * a.M + x;
                 const float4 cv = *reinterpret_cast<const float4*>(a.coef + off);
-                const float4 ov = *reinterpret_cast<const float4*>(so + kc * (TH * TW) + row * TW + 4 * q);
-                const float sc = a.scale[b * a.cout + kk];
-                const float v[4] = {cv.x, cv.y, cv.z, cv.w}, o[4] = {ov.x, ov.y, ov.z, ov.w};
+                const float v[4] = {cv.x, cv.y, cv.z, cv.w};
                 float t[4], r[4];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    t[j] = (kk == a.lowpass) ? 0.0f : softplusf(o[j]);
-                    r[j] = (fabsf(v[j] * sc) >= t[j]) ? v[j] : 0.0f;
+                for (int i = 0; i < 4; ++i) {
+                    t[i] = lowpass ? 0.0f : softplusf(acc[mt][nt][i] + bias);
+                    r[i] = (fabsf(v[i] * sc) >= t[i]) ? v[i] : 0.0f;
                 }
                 *reinterpret_cast<float4*>(a.out_f + off) = make_float4(r[0], r[1], r[2], r[3]);
                 if (a.tau) *reinterpret_cast<float4*>(a.tau + off) = make_float4(t[0], t[1], t[2], t[3]);
             }
-            __syncthreads();
         }
     } else {
         // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel
+        unsigned short* s_out = smem + HH * HW * Pix<CINP>::value;
         float lsum = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
@@ -399,7 +388,8 @@ __global__ void k_pack_bias(const float* __restrict__ b, float* __restrict__ out
 template <int CINP, int COUTP, int MODE, int OUTC = 32>
 hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
     const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC>);
-    const size_t lds = conv_lds_bytes<CINP, OUTC>();
+    // the shrink epilogue (MODE 2) works from registers and needs only the staged input tile
+    const size_t lds = MODE == 2 ? (size_t)HH * HW * Pix<CINP>::value * 2 : conv_lds_bytes<CINP, OUTC>();
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
