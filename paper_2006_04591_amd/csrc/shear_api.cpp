@@ -1303,33 +1303,30 @@ int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, floa
         return fail(SHEAR_E_SIZE, "learned shrinkage needs K <= 64, rows % 8 == 0 and cols % 128 == 0");
     const int K = s->K, N = s->rows, M = s->cols;
     const size_t act = (size_t)batch * N * M * 32 * 2;  // one bfloat16 activation tensor
-    const size_t zb = (size_t)batch * N * M * shear::shrink_cinp(K) * 2;
     const size_t sc = ((size_t)batch * K * sizeof(float) + 255) & ~(size_t)255;
-    if ((rc = ensure_ws2(s, sc + 2 * act + zb)) != SHEAR_OK) return rc;
+    if ((rc = ensure_ws2(s, sc + 2 * act)) != SHEAR_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     char* w = (char*)s->ws2;
     float* scale = (float*)w;
     void* h1 = w + sc;
     void* h2 = w + sc + act;
-    unsigned short* z = (unsigned short*)(w + sc + 2 * act);
     const shear::ShrinkLayout L = shear::shrink_layout(K);
     const char* p = (const char*)packed;
     hipError_t e = shear::launch_inv_scale(sigma, s->rms_dev, scale, batch, K, st);
     if (e != hipSuccess) return hip_fail(e, "scale launch");
-    if ((e = shear::launch_pack_z(coeffs, scale, z, K, N, M, batch, st)) != hipSuccess) return hip_fail(e, "z packing");
     shear::ConvArgs a{};
     a.N = N;
     a.M = M;
     a.scale = scale;
     a.lowpass = K - 1;
-    // layer 1: z -> h1
-    a.in = z;
+    // layer 1: z = bf16(c scale), staged from the coefficients inside the layer -> h1
+    a.coef = coeffs;
     a.W = (const unsigned short*)(p + L.w1);
     a.bias = (const float*)(p + L.b1);
     a.out_bf = h1;
     a.cin = K;
     a.cout = 32;
-    if ((e = shear::launch_conv(0, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 1 launch");
+    if ((e = shear::launch_conv(6, K, a, batch, st)) != hipSuccess) return hip_fail(e, "layer 1 launch");
     // layer 2: h1 -> h2
     a.in = h1;
     a.W = (const unsigned short*)(p + L.w2);

@@ -61,7 +61,8 @@ hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, in
 hipError_t launch_pack_z(const float* c, const float* scale, unsigned short* z, int K, int N, int M, int batch,
                          hipStream_t st);
 // layer 0, 1, 2: inference layers; 3: last layer with the training epilogue; 4: backward data from 32
-// gradient channels; 5: backward data from shrink_cinp(K) gradient channels.
+// gradient channels; 5: backward data from shrink_cinp(K) gradient channels; 6: layer 0 with its input
+// staged straight from the FP32 coefficients (coef, scale, cin = K) instead of the packed z.
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st);
 // weight gradients of layer 0, 1 or 2 (partials of `blocks` blocks of 32-pixel x 8-row tiles)
 hipError_t launch_wgrad(int layer, int K, const WgradArgs& a, int blocks, hipStream_t st);

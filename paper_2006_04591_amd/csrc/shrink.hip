@@ -48,10 +48,13 @@ struct Pix {
     static constexpr int value = CINP + 8;  // bf16 per staged pixel: 16 bytes of padding against bank conflicts
 };
 
-// staged output channels: the 32 hidden channels, or the padded gradient planes of layer 2's training epilogue
-template <int CINP, int OUTC>
+// LDS of a conv block: the staged input tile; the bf16 output tile (the 32 hidden channels, or the
+// padded gradient planes of layer 2's training epilogue) reuses it once the products are done.
+// The shrink epilogue (MODE 2) works from registers.
+template <int CINP, int OUTC, int MODE>
 constexpr size_t conv_lds_bytes() {
-    return (size_t)HH * HW * Pix<CINP>::value * 2 + (size_t)TH * TW * OUTC * 2;
+    constexpr size_t in = (size_t)HH * HW * Pix<CINP>::value * 2, out = (size_t)TH * TW * OUTC * 2;
+    return (MODE == 2 || in >= out) ? in : out;
 }
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
@@ -68,6 +71,41 @@ __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int 
         const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
         const uint4 v = in[(((size_t)b * N + y) * M + x) * CH + ch];
         *reinterpret_cast<uint4*>(s + (yy * HW + xx) * PIX + ch * 8) = v;
+    }
+}
+
+// Stages the halo tile of one image straight from the FP32 channel-first coefficient planes:
+// z = bf16(c x scale[b][k]) channel-last, zero beyond the a.cin real channels (the values
+// k_pack_z would write). The TW interior pixels of a tile row are read as aligned 16-byte
+// vectors, the two halo columns one value each.
+template <int CINP>
+__device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0) {
+    constexpr int PIX = Pix<CINP>::value, QW = TW / 4;
+    const int N = a.N, M = a.M, K = a.cin;
+    for (int i = threadIdx.x; i < CINP * HH * QW; i += THREADS) {
+        const int q = i % QW, yy = (i / QW) % HH, k = i / (QW * HH);
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        float sc = 0.0f;
+        if (k < K) {
+            const int y = (y0 + yy - 1 + N) & (N - 1);
+            v = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
+            sc = a.scale[b * K + k];
+        }
+        unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + k;
+        d[0] = f2bf(v.x * sc);
+        d[PIX] = f2bf(v.y * sc);
+        d[2 * PIX] = f2bf(v.z * sc);
+        d[3 * PIX] = f2bf(v.w * sc);
+    }
+    for (int i = threadIdx.x; i < CINP * HH * 2; i += THREADS) {
+        const int side = i % 2, yy = (i / 2) % HH, k = i / (2 * HH);
+        const int xx = side ? HW - 1 : 0;
+        float v = 0.0f;
+        if (k < K) {
+            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
+            v = a.coef[(((size_t)b * K + k) * N + y) * M + x] * a.scale[b * K + k];
+        }
+        s[(yy * HW + xx) * PIX + k] = f2bf(v);
     }
 }
 
@@ -135,7 +173,8 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
 //   bf16 channel-last planes [b][y][x][OUTC] (zero beyond K and on the low-pass plane);
 // MODE 4 (training, backward data): gradient planes -> conv with flipped, transposed weights, times the relu
 //   mask of the saved activation (mask_act > 0) -> bf16 gradient activations.
-template <int CINP, int COUTP, int MODE, int OUTC = 32>
+// COEF_IN: the input is staged from the coefficients (stage_coef) instead of a.in.
+template <int CINP, int COUTP, int MODE, int OUTC = 32, bool COEF_IN = false>
 __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     constexpr int NT = COUTP / 16;
     extern __shared__ unsigned short smem[];
@@ -143,7 +182,11 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     const int tx = a.M / TW, ty = a.N / TH;
     const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, b = blockIdx.x / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
-    stage<CINP>(a, s_in, b, y0, x0);
+    if constexpr (COEF_IN) {
+        stage_coef<CINP>(a, s_in, b, y0, x0);
+    } else {
+        stage<CINP>(a, s_in, b, y0, x0);
+    }
     __syncthreads();
     f32x4 acc[4][NT];
     mma<CINP, COUTP>(a, s_in, acc);
@@ -177,8 +220,10 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
             }
         }
     } else {
-        // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel
-        unsigned short* s_out = smem + HH * HW * Pix<CINP>::value;
+        // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel;
+        // the output tile overwrites the staged input once every wave is done reading it
+        unsigned short* s_out = smem;
+        __syncthreads();
         float lsum = 0.0f;
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
@@ -385,17 +430,17 @@ __global__ void k_pack_bias(const float* __restrict__ b, float* __restrict__ out
     if (i < np) out[i] = i < n ? b[i] : 0.0f;
 }
 
-template <int CINP, int COUTP, int MODE, int OUTC = 32>
+template <int CINP, int COUTP, int MODE, int OUTC = 32, bool COEF_IN = false>
 hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
-    const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC>);
-    // the shrink epilogue (MODE 2) works from registers and needs only the staged input tile
-    const size_t lds = MODE == 2 ? (size_t)HH * HW * Pix<CINP>::value * 2 : conv_lds_bytes<CINP, OUTC>();
+    const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC, COEF_IN>);
+    const size_t lds = conv_lds_bytes<CINP, OUTC, MODE>();
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const size_t blocks = (size_t)batch * (a.N / TH) * (a.M / TW);
-    hipLaunchKernelGGL((k_conv3x3<CINP, COUTP, MODE, OUTC>), dim3((unsigned)blocks), dim3(THREADS), lds, st, a);
+    hipLaunchKernelGGL((k_conv3x3<CINP, COUTP, MODE, OUTC, COEF_IN>), dim3((unsigned)blocks), dim3(THREADS), lds, st,
+                       a);
     return hipGetLastError();
 }
 
@@ -461,6 +506,9 @@ hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, in
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st) {
     if (layer == 0) return shrink_cinp(K) == 32 ? conv_t<32, 32, 1>(a, batch, st) : conv_t<64, 32, 1>(a, batch, st);
     if (layer == 1) return conv_t<32, 32, 1>(a, batch, st);
+    if (layer == 6)  // layer 1 staged straight from the coefficients (a.coef, a.scale, a.cin = K)
+        return shrink_cinp(K) == 32 ? conv_t<32, 32, 1, 32, true>(a, batch, st)
+                                    : conv_t<64, 32, 1, 32, true>(a, batch, st);
     if (layer == 3) {  // training: last layer with the loss epilogue, gradient planes of shrink_cinp(K) channels
         if (shrink_cinp(K) == 32) {
             switch (shrink_coutp(K)) {
