@@ -41,7 +41,17 @@ __device__ __forceinline__ unsigned short f2bf(float f) {
 }
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float(((unsigned)h) << 16); }
 
-__device__ __forceinline__ float softplusf(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+// softplus(x) = max(x, 0) + log1p(u), u = e^{-|x|} in (0, 1], from the hardware exponential and
+// logarithm (relative error ~1e-6, far inside the threshold tolerance). log1p(u) is taken as
+// log(w) u / (w - 1) with w = 1 + u rounded, which cancels the rounding of w (Goldberg, 1991,
+// "What every computer scientist should know about floating-point arithmetic", Theorem 4);
+// when w rounds to 1, log1p(u) = u to working precision.
+__device__ __forceinline__ float softplusf(float x) {
+    const float u = __expf(-fabsf(x));
+    const float w = 1.0f + u;
+    const float l = (w == 1.0f) ? u : __logf(w) * (u * __builtin_amdgcn_rcpf(w - 1.0f));
+    return fmaxf(x, 0.0f) + l;
+}
 
 template <int CINP>
 struct Pix {
