@@ -146,7 +146,9 @@ __global__ __launch_bounds__(THREADS) void k_pack_z(const float* __restrict__ c,
 
 // out[pixel][co] accumulators of a wavefront: 4 m-tiles (16 pixels of one row) x NT n-tiles.
 template <int CINP, int COUTP>
-__device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, f32x4 (&acc)[4][COUTP / 16]) {
+// (output channels co0 .. co0 + COUTP - 1 of the packed weights)
+__device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, f32x4 (&acc)[4][COUTP / 16],
+                                    int co0 = 0) {
     constexpr int PIX = Pix<CINP>::value, NT = COUTP / 16;
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lk = 8 * (l / 16);
@@ -163,7 +165,8 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
             bf16x8 bfr[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                bfr[nt] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(nt * 16 + lr) * 9 + tap) * CINP + kc * 32 + lk);
+                bfr[nt] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(co0 + nt * 16 + lr) * 9 + tap) * CINP +
+                                                           kc * 32 + lk);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int row = 2 * w + mt / 2, xs = (mt % 2) * 16;
@@ -198,17 +201,21 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         stage<CINP>(a, s_in, b, y0, x0);
     }
     __syncthreads();
-    f32x4 acc[4][NT];
-    mma<CINP, COUTP>(a, s_in, acc);
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lm = 4 * (l / 16);
     if constexpr (MODE == 2) {
         // o = acc + bias, tau = softplus(o) (0 on the low-pass plane), keep |c scale| >= tau. A lane
         // holds 4 consecutive pixels of one channel, so it reads and writes the channel-first
-        // coefficient planes directly as 16-byte vectors.
+        // coefficient planes directly as 16-byte vectors. At most 32 output channels per pass over
+        // the staged tile, so that fewer accumulators leave room for more waves per SIMD.
+        constexpr int CG = COUTP > 32 ? 32 : COUTP, NG = CG / 16;
+#pragma unroll 1
+        for (int c0 = 0; c0 < COUTP; c0 += CG) {
+        f32x4 acc[4][NG];
+        mma<CINP, CG>(a, s_in, acc, c0);
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int k = nt * 16 + lr;
+        for (int nt = 0; nt < NG; ++nt) {
+            const int k = c0 + nt * 16 + lr;
             if (k >= a.cout) continue;
             const float bias = a.bias[k];
             const float sc = a.scale[b * a.cout + k];
@@ -229,7 +236,10 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
                 if (a.tau) *reinterpret_cast<float4*>(a.tau + off) = make_float4(t[0], t[1], t[2], t[3]);
             }
         }
+        }
     } else {
+        f32x4 acc[4][NT];
+        mma<CINP, COUTP>(a, s_in, acc);
         // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel;
         // the output tile overwrites the staged input once every wave is done reading it
         unsigned short* s_out = smem;
