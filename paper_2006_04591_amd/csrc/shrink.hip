@@ -61,25 +61,32 @@ struct Pix {
 // LDS of a conv block: the staged input tile; the bf16 output tile (the 32 hidden channels, or the
 // padded gradient planes of layer 2's training epilogue) reuses it once the products are done.
 // The shrink epilogue (MODE 2) works from registers.
+// Input channels are staged at most 32 at a time (a layer with 64 input channels stages and
+// multiplies twice), which keeps the tile at 27 KB.
+template <int CINP>
+constexpr int staged_ch() {
+    return CINP > 32 ? 32 : CINP;
+}
 template <int CINP, int OUTC, int MODE>
 constexpr size_t conv_lds_bytes() {
-    constexpr size_t in = (size_t)HH * HW * Pix<CINP>::value * 2, out = (size_t)TH * TW * OUTC * 2;
+    constexpr size_t in = (size_t)HH * HW * Pix<staged_ch<CINP>()>::value * 2, out = (size_t)TH * TW * OUTC * 2;
     return (MODE == 2 || in >= out) ? in : out;
 }
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
 
-// Stages the halo tile of one image from bfloat16 channel-last activations with CINP channels.
-template <int CINP>
-__device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int b, int y0, int x0) {
-    constexpr int PIX = Pix<CINP>::value;
+// Stages the halo tile of one image, channels cb .. cb + CS - 1, from bfloat16 channel-last
+// activations with CIN channels per pixel.
+template <int CIN, int CS>
+__device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int b, int y0, int x0, int cb) {
+    constexpr int PIX = Pix<CS>::value;
     const int N = a.N, M = a.M;
     const uint4* in = reinterpret_cast<const uint4*>(a.in);
-    constexpr int CH = CINP / 8;  // 16-byte chunks per pixel
+    constexpr int CH = CS / 8, CHI = CIN / 8;  // 16-byte chunks per staged / input pixel
     for (int i = threadIdx.x; i < HH * HW * CH; i += THREADS) {
         const int ch = i % CH, p = i / CH, xx = p % HW, yy = p / HW;
         const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-        const uint4 v = in[(((size_t)b * N + y) * M + x) * CH + ch];
+        const uint4 v = in[(((size_t)b * N + y) * M + x) * CHI + cb / 8 + ch];
         *reinterpret_cast<uint4*>(s + (yy * HW + xx) * PIX + ch * 8) = v;
     }
 }
@@ -88,12 +95,12 @@ __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int 
 // z = bf16(c x scale[b][k]) channel-last, zero beyond the a.cin real channels (the values
 // k_pack_z would write). The TW interior pixels of a tile row are read as aligned 16-byte
 // vectors, the two halo columns one value each.
-template <int CINP>
-__device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0) {
-    constexpr int PIX = Pix<CINP>::value, QW = TW / 4;
+template <int CS>
+__device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0, int cb) {
+    constexpr int PIX = Pix<CS>::value, QW = TW / 4;
     const int N = a.N, M = a.M, K = a.cin;
-    for (int i = threadIdx.x; i < CINP * HH * QW; i += THREADS) {
-        const int q = i % QW, yy = (i / QW) % HH, k = i / (QW * HH);
+    for (int i = threadIdx.x; i < CS * HH * QW; i += THREADS) {
+        const int q = i % QW, yy = (i / QW) % HH, kl = i / (QW * HH), k = cb + kl;
         float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
         float sc = 0.0f;
         if (k < K) {
@@ -101,21 +108,21 @@ __device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s,
             v = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
             sc = a.scale[b * K + k];
         }
-        unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + k;
+        unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + kl;
         d[0] = f2bf(v.x * sc);
         d[PIX] = f2bf(v.y * sc);
         d[2 * PIX] = f2bf(v.z * sc);
         d[3 * PIX] = f2bf(v.w * sc);
     }
-    for (int i = threadIdx.x; i < CINP * HH * 2; i += THREADS) {
-        const int side = i % 2, yy = (i / 2) % HH, k = i / (2 * HH);
+    for (int i = threadIdx.x; i < CS * HH * 2; i += THREADS) {
+        const int side = i % 2, yy = (i / 2) % HH, kl = i / (2 * HH), k = cb + kl;
         const int xx = side ? HW - 1 : 0;
         float v = 0.0f;
         if (k < K) {
             const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
             v = a.coef[(((size_t)b * K + k) * N + y) * M + x] * a.scale[b * K + k];
         }
-        s[(yy * HW + xx) * PIX + k] = f2bf(v);
+        s[(yy * HW + xx) * PIX + kl] = f2bf(v);
     }
 }
 
@@ -144,29 +151,34 @@ __global__ __launch_bounds__(THREADS) void k_pack_z(const float* __restrict__ c,
     }
 }
 
-// out[pixel][co] accumulators of a wavefront: 4 m-tiles (16 pixels of one row) x NT n-tiles.
-template <int CINP, int COUTP>
-// (output channels co0 .. co0 + COUTP - 1 of the packed weights)
-__device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, f32x4 (&acc)[4][COUTP / 16],
-                                    int co0 = 0) {
-    constexpr int PIX = Pix<CINP>::value, NT = COUTP / 16;
-    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const int lr = l % 16, lk = 8 * (l / 16);
+template <int NT>
+__device__ __forceinline__ void zero_acc(f32x4 (&acc)[4][NT]) {
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+}
+
+// out[pixel][co] accumulators of a wavefront: 4 m-tiles (16 pixels of one row) x NT n-tiles, added
+// to acc: output channels co0 .. co0 + COUTP - 1 of the packed weights (CINP input channels per
+// tap), input channels cb .. cb + CS - 1 staged in s.
+template <int CINP, int CS, int COUTP>
+__device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, f32x4 (&acc)[4][COUTP / 16], int co0,
+                                    int cb) {
+    constexpr int PIX = Pix<CS>::value, NT = COUTP / 16;
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int lr = l % 16, lk = 8 * (l / 16);
     const unsigned short* W = a.W;
 #pragma unroll 1
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = tap / 3, dx = tap % 3;
 #pragma unroll
-        for (int kc = 0; kc < CINP / 32; ++kc) {
+        for (int kc = 0; kc < CS / 32; ++kc) {
             bf16x8 bfr[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
                 bfr[nt] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(co0 + nt * 16 + lr) * 9 + tap) * CINP +
-                                                           kc * 32 + lk);
+                                                           cb + kc * 32 + lk);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int row = 2 * w + mt / 2, xs = (mt % 2) * 16;
@@ -195,12 +207,19 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     const int tx = a.M / TW, ty = a.N / TH;
     const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, b = blockIdx.x / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
-    if constexpr (COEF_IN) {
-        stage_coef<CINP>(a, s_in, b, y0, x0);
-    } else {
-        stage<CINP>(a, s_in, b, y0, x0);
+    constexpr int CS = staged_ch<CINP>();
+    static_assert(MODE != 2 || CS == CINP, "the shrink layer stages its whole input once");
+    auto stage_part = [&](int cb) {
+        if constexpr (COEF_IN) {
+            stage_coef<CS>(a, s_in, b, y0, x0, cb);
+        } else {
+            stage<CINP, CS>(a, s_in, b, y0, x0, cb);
+        }
+    };
+    if constexpr (MODE == 2) {
+        stage_part(0);
+        __syncthreads();
     }
-    __syncthreads();
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lm = 4 * (l / 16);
     if constexpr (MODE == 2) {
@@ -212,7 +231,8 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
 #pragma unroll 1
         for (int c0 = 0; c0 < COUTP; c0 += CG) {
         f32x4 acc[4][NG];
-        mma<CINP, CG>(a, s_in, acc, c0);
+        zero_acc(acc);
+        mma<CINP, CS, CG>(a, s_in, acc, c0, 0);
 #pragma unroll
         for (int nt = 0; nt < NG; ++nt) {
             const int k = c0 + nt * 16 + lr;
@@ -239,7 +259,14 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         }
     } else {
         f32x4 acc[4][NT];
-        mma<CINP, COUTP>(a, s_in, acc);
+        zero_acc(acc);
+#pragma unroll 1
+        for (int cb = 0; cb < CINP; cb += CS) {
+            if (cb > 0) __syncthreads();  // every wave is done with the previous part
+            stage_part(cb);
+            __syncthreads();
+            mma<CINP, CS, COUTP>(a, s_in, acc, 0, cb);
+        }
         // bf16 results through LDS, then 16-byte channel-last stores of OUTC channels per pixel;
         // the output tile overwrites the staged input once every wave is done reading it
         unsigned short* s_out = smem;
