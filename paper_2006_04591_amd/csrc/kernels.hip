@@ -23,8 +23,10 @@ namespace {
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// The fused multiply-adds are written out so that every kernel rounds a complex product the
+// same way (left to the compiler, contraction can differ between kernels that inline it).
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+    return make_float2(fmaf(a.x, b.x, -(a.y * b.y)), fmaf(a.x, b.y, a.y * b.x));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
@@ -613,6 +615,10 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
         n += (kx ? 1u : 0u) + (ky ? 1u : 0u);
     }
     fft<L, P, false>(v, s, t, twL);
+    // post-twiddles loaded before the barrier, ahead of the tile's stores
+    float2 tw[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) tw[i] = twM[kk + T * i];
 #pragma unroll
     for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
     __syncthreads();
@@ -630,7 +636,7 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
                 const float2 E = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
                 const float2 D = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
                 const float2 O = make_float2(D.y, -D.x);
-                X = cadd(E, cmul(twM[k], O));
+                X = cadd(E, cmul(tw[i], O));
             }
             st_stream(plane + xoff(row0 + r2, k, N), X);
         }
