@@ -179,8 +179,9 @@ int shear_shrink_pack(shear_system* s, const float* W1, const float* b1, const f
 /* coeffs (batch*K*rows*cols float32, device, as shear_forward writes them) ->
  * shrunk (same shape; must not overlap coeffs) and, if tau is non-NULL, the
  * thresholds tau (same shape, noise units). sigma: batch float32 (device),
- * the noise level of each image. The system keeps a workspace of
- * 64*batch*rows*cols bytes for the hidden activations. Asynchronous. */
+ * the noise level of each image. The system keeps a workspace of about
+ * 128*batch*rows*cols bytes for the two hidden activations (32 bfloat16
+ * channels each). Asynchronous. */
 int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, float* tau, int batch, const float* sigma,
                        const void* packed, void* hip_stream);
 
