@@ -308,15 +308,18 @@ __device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __rest
                                                 const float2* __restrict__ twM, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
     const int t = tid % T, r = tid / T;
+    const int r2 = tid % ROWS, kk = tid / ROWS;
     float2* s = lds + r * PITCH;
     float2 v[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = load(row0 + r, t + T * q);
+    // post-twiddle of column kk + T i as twM[kk] twM[T i]: one per-lane load, issued before any
+    // store of the tile, and the wave-uniform twM[T i] (scalar loads)
+    const float2 tw0 = twM[kk];
     fft<L, P, false>(v, s, t, twL);
 #pragma unroll
     for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
     __syncthreads();
-    const int r2 = tid % ROWS, kk = tid / ROWS;
     const float2* s2 = lds + r2 * PITCH;
 #pragma unroll
     for (int i = 0; i < P; ++i) {
@@ -330,7 +333,7 @@ __device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __rest
             const float2 E = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
             const float2 D = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
             const float2 O = make_float2(D.y, -D.x);  // (Z - conj Zm) / (2i)
-            X = cadd(E, cmul(twM[k], O));
+            X = cadd(E, cmul(i == 0 ? tw0 : cmul(tw0, twM[T * i]), O));
         }
         st_x<XS>(out_plane + xoff(row0 + r2, k, N), X);
     }
@@ -363,6 +366,9 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
     }
     __syncthreads();
     const int t = tid % T, r = tid / T;
+    // pre-twiddle of column t + T q as twM[t] twM[T q] (one per-lane load; twM[T q] is
+    // wave-uniform)
+    const float2 tw0 = twM[t];
     float2* s = lds + r * PITCH;
     float2 v[P];
     const float2 P0 = s[0];
@@ -376,7 +382,7 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
         }
         const float2 A = make_float2(X.x + Xm.x, X.y - Xm.y);  // X + conj(Xm)
         const float2 D = make_float2(X.x - Xm.x, X.y + Xm.y);  // X - conj(Xm)
-        const float2 B = cmul(D, cconj(twM[k]));
+        const float2 B = cmul(D, cconj(q == 0 ? tw0 : cmul(tw0, twM[T * q])));
         v[q] = make_float2(A.x - B.y, A.y + B.x);  // A + i B
     }
     __syncthreads();
