@@ -349,12 +349,26 @@ __device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane,
         twM, tid);
 }
 
-// packed spectra (panel layout) -> real rows, out = scale * unnormalised inverse
-template <int M, int P, int ROWS, bool XS = true>
+// packed spectra (panel layout) -> real rows, out = scale * unnormalised inverse.
+// TWLDS: the block copies the FFT's twiddles twL to LDS after the row scratches (L more
+// float2) while its tile loads are in flight, and the FFT passes read them there instead of
+// with vector-memory loads.
+template <int M, int P, int ROWS, bool XS = true, bool TWLDS = false>
 __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane, float* __restrict__ out_plane, int N,
                                              int row0, float2* lds, const float2* __restrict__ twL,
                                              const float2* __restrict__ twM, float scale, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
+    constexpr int TWN = TWLDS ? (L + ROWS * T - 1) / (ROWS * T) : 0;  // twiddles copied per thread
+    const int t = tid % T, r = tid / T;
+    // pre-twiddle of column t + T q as twM[t] twM[T q] (one per-lane load, issued with the tile's
+    // loads; twM[T q] is wave-uniform)
+    const float2 tw0 = twM[t];
+    float2 twv[TWN > 0 ? TWN : 1];
+#pragma unroll
+    for (int j = 0; j < TWN; ++j) {
+        const int i = tid + j * ROWS * T;
+        if (i < L) twv[j] = twL[i];
+    }
     {
         const int r2 = tid % ROWS, kk = tid / ROWS;
         float2* s2 = lds + r2 * PITCH;
@@ -364,11 +378,17 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
             s2[k] = ld_x<XS>(in_plane + xoff(row0 + r2, k, N));
         }
     }
+    const float2* twf = twL;
+    if constexpr (TWLDS) {
+        float2* stw = lds + ROWS * PITCH;
+#pragma unroll
+        for (int j = 0; j < TWN; ++j) {
+            const int i = tid + j * ROWS * T;
+            if (i < L) stw[i] = twv[j];
+        }
+        twf = stw;
+    }
     __syncthreads();
-    const int t = tid % T, r = tid / T;
-    // pre-twiddle of column t + T q as twM[t] twM[T q] (one per-lane load; twM[T q] is
-    // wave-uniform)
-    const float2 tw0 = twM[t];
     float2* s = lds + r * PITCH;
     float2 v[P];
     const float2 P0 = s[0];
@@ -386,7 +406,7 @@ __device__ __forceinline__ void row_c2r_tile(const float2* __restrict__ in_plane
         v[q] = make_float2(A.x - B.y, A.y + B.x);  // A + i B
     }
     __syncthreads();
-    fft<L, P, true>(v, s, t, twL);
+    fft<L, P, true>(v, s, t, twf);
     float2* dst = reinterpret_cast<float2*>(out_plane + (size_t)(row0 + r) * M);
 #pragma unroll
     for (int q = 0; q < P; ++q) st_stream(dst + t + T * q, cscale(v[q], scale));
@@ -561,13 +581,13 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(c
                                                                              const float2* __restrict__ twL,
                                                                              const float2* __restrict__ twM,
                                                                              float scale) {
-    constexpr int L = M / 2;
+    constexpr int L = M / 2, P = Pts<L>::value;
     extern __shared__ float2 lds[];
     const int nrb = N / ROWS;
     const int plane = blockIdx.x / nrb;
     const int row0 = (blockIdx.x % nrb) * ROWS;
-    row_c2r_tile<M, Pts<L>::value, ROWS>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL, twM,
-                                       scale, (int)threadIdx.x);
+    row_c2r_tile<M, P, ROWS, true, true>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL,
+                                         twM, scale, (int)threadIdx.x);
 }
 
 // Forward row stage, hard threshold and inverse row stage of one tile of a
@@ -1141,7 +1161,7 @@ hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes
 template <int M, int TAG, int ROWS>
 hipError_t rows_c2r_rt(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)ROWS * RowPitch<L, P>::value * sizeof(float2);
+    const size_t lds = ((size_t)ROWS * RowPitch<L, P>::value + L) * sizeof(float2);
     hipError_t e = set_lds(k_rows_c2r<M, TAG, ROWS>, lds);
     if (e != hipSuccess) return e;
     const size_t blocks = (size_t)planes * (d.N / ROWS);
