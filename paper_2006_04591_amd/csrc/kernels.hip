@@ -301,22 +301,42 @@ struct RowPitch {
     static constexpr int value = L + L / P + 1;
 };
 
-// load(row, i) returns samples 2i and 2i+1 of a row of the plane
-template <int M, int P, int ROWS, bool XS, typename Load>
+// load(row, i) returns samples 2i and 2i+1 of a row of the plane.
+// TWLDS: the FFT's twiddles twL are copied to LDS after the row scratches (L more float2)
+// while the tile loads are in flight, one barrier before the FFT, which then reads them there.
+template <int M, int P, int ROWS, bool XS, typename Load, bool TWLDS = false>
 __device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __restrict__ out_plane, int N, int row0,
                                                 float2* lds, const float2* __restrict__ twL,
                                                 const float2* __restrict__ twM, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
+    constexpr int TWN = TWLDS ? (L + ROWS * T - 1) / (ROWS * T) : 0;  // twiddles copied per thread
     const int t = tid % T, r = tid / T;
     const int r2 = tid % ROWS, kk = tid / ROWS;
     float2* s = lds + r * PITCH;
+    float2 twv[TWN > 0 ? TWN : 1];
+#pragma unroll
+    for (int j = 0; j < TWN; ++j) {
+        const int i = tid + j * ROWS * T;
+        if (i < L) twv[j] = twL[i];
+    }
     float2 v[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) v[q] = load(row0 + r, t + T * q);
     // post-twiddle of column kk + T i as twM[kk] twM[T i]: one per-lane load, issued before any
     // store of the tile, and the wave-uniform twM[T i] (scalar loads)
     const float2 tw0 = twM[kk];
-    fft<L, P, false>(v, s, t, twL);
+    const float2* twf = twL;
+    if constexpr (TWLDS) {
+        float2* stw = lds + ROWS * PITCH;
+#pragma unroll
+        for (int j = 0; j < TWN; ++j) {
+            const int i = tid + j * ROWS * T;
+            if (i < L) stw[i] = twv[j];
+        }
+        twf = stw;
+        __syncthreads();
+    }
+    fft<L, P, false>(v, s, t, twf);
 #pragma unroll
     for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
     __syncthreads();
@@ -339,14 +359,14 @@ __device__ __forceinline__ void row_r2c_tile_ld(const Load& load, float2* __rest
     }
 }
 
-template <int M, int P, int ROWS, bool XS = true>
+template <int M, int P, int ROWS, bool XS = true, bool TWLDS = false>
 __device__ __forceinline__ void row_r2c_tile(const float* __restrict__ in_plane, float2* __restrict__ out_plane, int N,
                                              int row0, float2* lds, const float2* __restrict__ twL,
                                              const float2* __restrict__ twM, const int tid) {
     const float2* src = reinterpret_cast<const float2*>(in_plane);
-    row_r2c_tile_ld<M, P, ROWS, XS>(
-        [src](int row, int i) { return ld_stream(src + (size_t)row * (M / 2) + i); }, out_plane, N, row0, lds, twL,
-        twM, tid);
+    auto ld = [src](int row, int i) { return ld_stream(src + (size_t)row * (M / 2) + i); };
+    row_r2c_tile_ld<M, P, ROWS, XS, decltype(ld), TWLDS>(
+        ld, out_plane, N, row0, lds, twL, twM, tid);
 }
 
 // packed spectra (panel layout) -> real rows, out = scale * unnormalised inverse.
@@ -544,8 +564,8 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(c
     const int nrb = N / ROWS;
     const int plane = blockIdx.x / nrb;
     const int row0 = (blockIdx.x % nrb) * ROWS;
-    row_r2c_tile<M, Pts<L>::value, ROWS>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0, lds, twL, twM,
-                                         (int)threadIdx.x);
+    row_r2c_tile<M, Pts<L>::value, ROWS, true, true>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0,
+                                                     lds, twL, twM, (int)threadIdx.x);
 }
 
 // Row stage of one inpainting iteration (Algorithm 3): the rows of
@@ -1143,7 +1163,7 @@ hipError_t set_lds(F* fn, size_t bytes) {
 template <int M, int TAG, int ROWS>
 hipError_t rows_r2c_rt(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)ROWS * RowPitch<L, P>::value * sizeof(float2);
+    const size_t lds = ((size_t)ROWS * RowPitch<L, P>::value + L) * sizeof(float2);
     hipError_t e = set_lds(k_rows_r2c<M, TAG, ROWS>, lds);
     if (e != hipSuccess) return e;
     const size_t blocks = (size_t)planes * (d.N / ROWS);
