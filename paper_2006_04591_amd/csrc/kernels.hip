@@ -621,7 +621,19 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
                                                 const float2* __restrict__ twL, const float2* __restrict__ twM,
                                                 float thr, unsigned* __restrict__ kept, const int tid) {
     constexpr int L = M / 2, T = L / P, PITCH = RowPitch<L, P>::value;
+    constexpr int TWN = (L + ROWS * T - 1) / (ROWS * T);  // FFT twiddles copied to LDS per thread
     const int r2 = tid % ROWS, kk = tid / ROWS;
+    const int t = tid % T, r = tid / T;
+    // Twiddles, all loaded with the tile: the FFTs' twL go to LDS after the row scratches
+    // (L more float2); the pre- and post-twiddles of columns t + T q and kk + T i are a
+    // per-lane base (twM[t], twM[kk]) times the wave-uniform twM[T q].
+    float2 twv[TWN];
+#pragma unroll
+    for (int j = 0; j < TWN; ++j) {
+        const int i = tid + j * ROWS * T;
+        if (i < L) twv[j] = twL[i];
+    }
+    const float2 twa = twM[t], twb = twM[kk];
     {
         float2* s2 = lds + r2 * PITCH;
 #pragma unroll
@@ -630,8 +642,13 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
             s2[k] = ld_stream(plane + xoff(row0 + r2, k, N));
         }
     }
+    float2* stw = lds + ROWS * PITCH;
+#pragma unroll
+    for (int j = 0; j < TWN; ++j) {
+        const int i = tid + j * ROWS * T;
+        if (i < L) stw[i] = twv[j];
+    }
     __syncthreads();
-    const int t = tid % T, r = tid / T;
     float2* s = lds + r * PITCH;
     float2 v[P];
     {
@@ -646,12 +663,12 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
             }
             const float2 A = make_float2(X.x + Xm.x, X.y - Xm.y);
             const float2 D = make_float2(X.x - Xm.x, X.y + Xm.y);
-            const float2 B = cmul(D, cconj(twM[k]));
+            const float2 B = cmul(D, cconj(q == 0 ? twa : cmul(twa, twM[T * q])));
             v[q] = make_float2(A.x - B.y, A.y + B.x);
         }
     }
     __syncthreads();
-    fft<L, P, true>(v, s, t, twL);
+    fft<L, P, true>(v, s, t, stw);
     // v[q] holds the coefficients at columns 2(t + T q) and 2(t + T q) + 1
     unsigned n = 0;
 #pragma unroll
@@ -660,11 +677,7 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
         v[q] = make_float2(kx ? v[q].x : 0.0f, ky ? v[q].y : 0.0f);
         n += (kx ? 1u : 0u) + (ky ? 1u : 0u);
     }
-    fft<L, P, false>(v, s, t, twL);
-    // post-twiddles loaded before the barrier, ahead of the tile's stores
-    float2 tw[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) tw[i] = twM[kk + T * i];
+    fft<L, P, false>(v, s, t, stw);
 #pragma unroll
     for (int q = 0; q < P; ++q) s[t + T * q] = v[q];
     __syncthreads();
@@ -682,7 +695,7 @@ __device__ __forceinline__ void row_thresh_tile(float2* __restrict__ plane, int 
                 const float2 E = make_float2(0.5f * (Z.x + Zm.x), 0.5f * (Z.y - Zm.y));
                 const float2 D = make_float2(0.5f * (Z.x - Zm.x), 0.5f * (Z.y + Zm.y));
                 const float2 O = make_float2(D.y, -D.x);
-                X = cadd(E, cmul(tw[i], O));
+                X = cadd(E, cmul(i == 0 ? twb : cmul(twb, twM[T * i]), O));
             }
             st_stream(plane + xoff(row0 + r2, k, N), X);
         }
@@ -1213,7 +1226,7 @@ template <int M, int ROWS>
 hipError_t rows_thresh_rt(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
                           hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)ROWS * RowPitch<L, P>::value * sizeof(float2);
+    const size_t lds = ((size_t)ROWS * RowPitch<L, P>::value + L) * sizeof(float2);  // + the FFT twiddles
     hipError_t e = set_lds(k_rows_thresh<M, ROWS>, lds);
     if (e != hipSuccess) return e;
     const size_t blocks = (size_t)nplanes * (d.N / ROWS);
