@@ -227,7 +227,9 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         // holds 4 consecutive pixels of one channel, so it reads and writes the channel-first
         // coefficient planes directly as 16-byte vectors. At most 32 output channels per pass over
         // the staged tile, so that fewer accumulators leave room for more waves per SIMD.
-        constexpr int CG = COUTP > 32 ? 32 : COUTP, NG = CG / 16;
+        // (48 padded channels go in three passes of 16: a pass never reads weight rows past COUTP)
+        constexpr int CG = COUTP <= 32 ? COUTP : (COUTP % 32 == 0 ? 32 : 16), NG = CG / 16;
+        static_assert(COUTP % CG == 0, "the passes cover the padded output channels exactly");
 #pragma unroll 1
         for (int c0 = 0; c0 < COUTP; c0 += CG) {
         f32x4 acc[4][NG];
