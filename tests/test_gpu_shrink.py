@@ -6,9 +6,11 @@ values before rounding differ from the GPU's by the FP32 accumulation error
 (about 1e-7 relative), so a value that lands within that distance of a
 bfloat16 rounding boundary can round to the neighbouring bfloat16 (2^-8
 relative) on one side only. Such flips are rare: they change tau by far less
-than 1e-3 in relative L2, the bound used here. The keep/zero decision is
-compared where |z| is not within 1e-3 tau of tau; inside that band either
-decision is valid, and the band holds only a small fraction of the coefficients.
+than 1e-3 in relative L2, the bound used here, though a single tau can move by
+a few 1e-3. The keep/zero decision compares |z| with the network's own tau, so
+where |z| lies within 1e-3 tau of the oracle's tau, or between the GPU's and
+the oracle's tau, either decision is valid; elsewhere the decisions must be
+equal, and the ambiguous set must stay a small fraction of the coefficients.
 """
 import numpy as np
 import pytest
@@ -47,7 +49,11 @@ def _check(got_c, got_t, c32, sigma, rms, p):
     want_c, want_t = OS.shrink(c32.astype(np.float64), sigma, rms, p)
     assert _rel(got_t, want_t) <= TAU_TOL
     z = c32.astype(np.float64) / (sigma * rms[:, None, None])
-    clear = np.abs(np.abs(z) - want_t) > 1e-3 * np.maximum(want_t, 1e-3)
+    az = np.abs(z)
+    lo = np.minimum(got_t, want_t) * (1 - 1e-6)
+    hi = np.maximum(got_t, want_t) * (1 + 1e-6)
+    between = (az >= lo) & (az <= hi)
+    clear = (np.abs(az - want_t) > 1e-3 * np.maximum(want_t, 1e-3)) & ~between
     assert clear.mean() > 0.99
     assert np.array_equal(got_c[clear], want_c[clear])
     # inside the band, each output is either the coefficient or zero
@@ -133,3 +139,27 @@ def test_shrink_errors(gpu):
         assert e.value.name == "SHEAR_E_SIZE"
         with pytest.raises(ValueError):
             ShrinkNet(s, {**_params_dict(p), "W1": np.zeros((32, 3, 3, 3))})
+
+
+@pytest.mark.parametrize("K", [33, 48, 64])
+def test_shrink_wide_channel_counts(gpu, K):
+    """K above 32 (user banks, 64x128, B=2): layer 1 stages its 64 padded input channels in two
+    parts, and the shrink layer covers 48 padded output channels in three passes of 16, 64 in two
+    of 32."""
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say(f"case: shrink 64x128 K={K} B=2")
+    rng = np.random.default_rng(100 + K)
+    S = np.fft.fft2(rng.standard_normal((K, 64, 128)))
+    rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+    c32 = (rng.standard_normal((2, K, 64, 128)) * 30.0 * rms[None, :, None, None]).astype(np.float32)
+    sig = np.array([15.0, 40.0])
+    p = OS.init_params(K, seed=K, tau0=2.0)
+    p.W3 *= 10.0
+    p = OS.ShrinkParams(p.W1, p.b1 + 0.1, p.W2, p.b2 - 0.05, p.W3, p.b3)
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        net = ShrinkNet(s, _params_dict(p))
+        out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        torch.cuda.synchronize()
+        for b in range(2):
+            _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], rms, p)

@@ -100,3 +100,38 @@ def test_training_reduces_loss(gpu):
         e1 = float(((net.apply(a, sg) - b) ** 2).sum())
         e0 = float(((start.apply(a, sg) - b) ** 2).sum())
         assert e1 < e0
+
+
+@pytest.mark.parametrize("K", [40, 64])
+def test_train_step_gradients_wide_channel_counts(gpu, K):
+    """K above 32 (user banks, 64x128, B=2): 64 padded input channels of layer 1 (two staging
+    parts in the forward and in the backward data of the last layer, 64-channel weight
+    gradients) and 48 or 64 padded output channels of the last layer."""
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say(f"case: shrink training gradients 64x128 K={K} B=2")
+    rng = np.random.default_rng(200 + K)
+    S = np.fft.fft2(rng.standard_normal((K, 64, 128)))
+    rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+    sig = np.array([20.0, 35.0])
+    cc = (rng.standard_normal((2, K, 64, 128)) * 20.0 * rms[None, :, None, None]).astype(np.float32)
+    cn = (cc + rng.standard_normal(cc.shape) * sig[:, None, None, None] * rms[None, :, None, None]).astype(np.float32)
+    p = _net_params(K, 50 + K)
+    T = 0.5
+    scale = 1.0 / (2 * (K - 1) * 64 * 128)
+    L = 0.0
+    want = {n: 0.0 for n in ("W1", "b1", "W2", "b2", "W3", "b3")}
+    for b in range(2):
+        Lb, gb = OS.train_loss(cn[b], cc[b], sig[b], rms, p, T, scale, rounded=True)
+        L += Lb
+        for n in want:
+            want[n] = want[n] + gb[n]
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        net = ShrinkNet(s, {n: getattr(p, n) for n in ShrinkNet.NAMES})
+        loss = net.train_step(_to(cn, gpu), _to(cc, gpu), _to(sig, gpu), lr=0.0, temperature=T)
+        torch.cuda.synchronize()
+        assert abs(float(loss) - L) <= 1e-2 * L
+        for n in want:
+            e = _rel(net.grad(n).cpu().numpy(), want[n])
+            print(f"grad {n}: rel L2 {e:.2e}")
+            assert e <= 2e-2, n
