@@ -272,11 +272,18 @@ struct Pts {
 constexpr int RB = 16;       // rows per block in the standalone row passes over images
 constexpr int RB_COEF = 32;  // ... over coefficient planes (when the plane has that many rows)
 
-// rows per block of the coefficient row passes: RB_COEF, or fewer where that would exceed 1024 threads
+// rows per block of a standalone row pass: R, or fewer where that would exceed 512 threads (at
+// M = 1024 a 1024-thread block of 16 rows filled its CU alone, so the phases of one block could
+// not overlap another's)
+template <int M, int R>
+constexpr int cap_rows() {
+    constexpr int T = (M / 2) / Pts<M / 2>::value;
+    return (R * T <= 512) ? R : 512 / T;
+}
+// ... of the coefficient row passes
 template <int M>
 constexpr int coef_rows() {
-    constexpr int T = (M / 2) / Pts<M / 2>::value;
-    return (RB_COEF * T <= 1024) ? RB_COEF : 1024 / T;
+    return cap_rows<M, RB_COEF>();
 }
 
 template <bool REAL>
@@ -1188,7 +1195,7 @@ hipError_t rows_r2c_rt(const DevPlan& d, const float* in, float2* out, int plane
 template <int M, int TAG>
 hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
     if (TAG == 1 && d.N >= coef_rows<M>()) return rows_r2c_rt<M, TAG, coef_rows<M>()>(d, in, out, planes, st);
-    return rows_r2c_rt<M, TAG, RB>(d, in, out, planes, st);
+    return rows_r2c_rt<M, TAG, cap_rows<M, RB>()>(d, in, out, planes, st);
 }
 
 template <int M, int TAG, int ROWS>
@@ -1206,7 +1213,7 @@ hipError_t rows_c2r_rt(const DevPlan& d, const float2* in, float* out, int plane
 // (the c2r passes measured faster with 16-row tiles, the coefficient r2c pass with 32)
 template <int M, int TAG>
 hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
-    return rows_c2r_rt<M, TAG, RB>(d, in, out, planes, scale, st);
+    return rows_c2r_rt<M, TAG, cap_rows<M, RB>()>(d, in, out, planes, scale, st);
 }
 
 template <int M>
@@ -1239,7 +1246,7 @@ template <int M>
 hipError_t rows_thresh_t(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
                          hipStream_t st) {
     if (d.N >= coef_rows<M>()) return rows_thresh_rt<M, coef_rows<M>()>(d, planes, nplanes, thr, kept, st);
-    return rows_thresh_rt<M, RB>(d, planes, nplanes, thr, kept, st);
+    return rows_thresh_rt<M, cap_rows<M, RB>()>(d, planes, nplanes, thr, kept, st);
 }
 
 // filters per group for kg requested groups, and the groups that gives
