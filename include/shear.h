@@ -273,10 +273,12 @@ int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_
 int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv);
 
 /* Autotuner: times the column passes of both directions for every compiled
- * panel width and filter split in {1, 2, 4, 8} (at most K) on the system's
- * workspace at this batch size (clearing the workspace first), keeps the
- * fastest of each direction (shear_set_schedule) and reports it through the
- * out-pointers (any may be NULL). Synchronous: waits for the device,
+ * panel width and filter split in {1, 2, 4, 8} (at most K; the forward also
+ * tries 16 and 32 when batch * cols/16 is below the device's compute units)
+ * on the system's workspace at this batch size (clearing the workspace
+ * first), five interleaved rounds keeping each candidate's fastest launch,
+ * keeps the fastest of each direction (shear_set_schedule) and reports it
+ * through the out-pointers (any may be NULL). Synchronous: waits for the device,
  * allocates the workspace for batch if needed, uses the null stream. Drops
  * any captured inpainting graph. */
 int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv);

@@ -1044,9 +1044,16 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
     if (rc != SHEAR_OK) return rc;
     std::vector<int> pws = {8};
     if (s->cols / 2 >= 16) pws.insert(pws.begin(), 16);
-    std::vector<int> kgs;
+    // filter splits: up to 8 groups in the inverse (each group adds a partial-sum plane per image);
+    // the forward, which needs no partial sums, also tries 16 and 32 when the batch's panels alone
+    // (at 8 columns) would leave the device's compute units idle
+    std::vector<int> kgs, kgs_fwd;
     for (int kg : {1, 2, 4, 8})
         if (kg <= s->K) kgs.push_back(kg);
+    kgs_fwd = kgs;
+    if ((long long)batch * (s->cols / 2 / 8) < (long long)s->cus)
+        for (int kg : {16, 32})
+            if (kg <= s->K) kgs_fwd.push_back(kg);
     // the workspace and chunk of the largest filter split (its partial sums need the most room)
     const shear::DevPlan saved = s->plan;
     s->plan.kg_inv = kgs.back();
@@ -1070,34 +1077,37 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
         if (e0) (void)hipEventDestroy(e0);
         return hip_fail(e, "hipEventCreate");
     }
-    constexpr int kReps = 3;
+    // each candidate is timed once per round, rounds interleaved, and keeps its fastest launch:
+    // drifts of the device's clocks and interference hit every candidate alike
+    constexpr int kRounds = 5;
     for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-        float best = -1.0f;
-        int pick_pw = pws[0], pick_kg = 1;
-        for (int pw : pws) {
-            for (int kg : kgs) {
+        std::vector<std::pair<int, int>> cand;
+        for (int pw : pws)
+            for (int kg : (dir == 0 ? kgs_fwd : kgs)) cand.emplace_back(pw, kg);
+        std::vector<float> best(cand.size(), -1.0f);
+        for (int round = 0; round <= kRounds && e == hipSuccess; ++round) {  // round 0 warms up
+            for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
                 shear::DevPlan d = s->plan;
-                (dir == 0 ? d.pw_fwd : d.pw_inv) = pw;
-                (dir == 0 ? d.kg_fwd : d.kg_inv) = kg;
-                auto launch = [&] {
-                    return dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
-                                    : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, part, nullptr);
-                };
-                if ((e = launch()) != hipSuccess) break;  // warm-up
+                (dir == 0 ? d.pw_fwd : d.pw_inv) = cand[ci].first;
+                (dir == 0 ? d.kg_fwd : d.kg_inv) = cand[ci].second;
                 if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) break;
-                for (int r = 0; r < kReps && e == hipSuccess; ++r) e = launch();
+                e = dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
+                             : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, part, nullptr);
                 if (e != hipSuccess) break;
                 if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
                 float ms = 0.0f;
                 if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-                if (best < 0.0f || ms < best) {
-                    best = ms;
-                    pick_pw = pw;
-                    pick_kg = kg;
-                }
+                if (round > 0 && (best[ci] < 0.0f || ms < best[ci])) best[ci] = ms;
             }
-            if (e != hipSuccess) break;
         }
+        int pick_pw = pws[0], pick_kg = 1;
+        float pick = -1.0f;
+        for (size_t ci = 0; ci < cand.size(); ++ci)
+            if (best[ci] >= 0.0f && (pick < 0.0f || best[ci] < pick)) {
+                pick = best[ci];
+                pick_pw = cand[ci].first;
+                pick_kg = cand[ci].second;
+            }
         if (e == hipSuccess) {
             (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick_pw;
             (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = pick_kg;

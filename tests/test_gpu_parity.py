@@ -398,7 +398,7 @@ def test_schedules_agree_and_autotune(gpu, lib, N, M, J, B):
         x = _to(xh, gpu)
         res = {}
         for pw in (16, 8):
-            for kg in (1, 3, 8):
+            for kg in (1, 3, 8, 16):
                 s.set_schedule(pw, pw, kg, kg)
                 c = s.forward(x)
                 res[(pw, kg)] = (c, s.inverse(c), s.adjoint(c))
@@ -414,7 +414,8 @@ def test_schedules_agree_and_autotune(gpu, lib, N, M, J, B):
         assert _rel(yk, OT.inverse_plain(c_in, ref.spectra, ref.W)) <= TOL
         assert _rel(y0.cpu().numpy(), xh) <= TOL
         pf, pi, kf, ki = s.autotune(B)
-        assert pf in (8, 16) and pi in (8, 16) and 1 <= kf <= 8 and 1 <= ki <= 8
+        # the forward may split up to 32 ways at small batches, the inverse up to 8
+        assert pf in (8, 16) and pi in (8, 16) and kf in (1, 2, 4, 8, 16, 32) and kf <= ref.K and ki in (1, 2, 4, 8)
         c = s.forward(x)
         y = s.inverse(c)
         torch.cuda.synchronize()
