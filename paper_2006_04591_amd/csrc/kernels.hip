@@ -297,8 +297,9 @@ __device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, flo
 
 // ---------------------------------------------------------------- row tiles
 // A tile is ROWS consecutive rows of one plane, handled by ROWS * (L/P) threads
-// (thread t of row r is threadIdx.x = t + (L/P) r). lds holds ROWS * (L + 1) float2.
-// The caller separates consecutive tiles that reuse lds with a barrier.
+// (thread t of row r is threadIdx.x = t + (L/P) r). lds holds ROWS * RowPitch<L, P>
+// float2, plus L twiddles where a tile copies its FFT's twiddles there. The caller
+// separates consecutive tiles that reuse lds with a barrier.
 
 // real rows -> packed spectra, plane out in the panel layout (xoff)
 // per-row LDS pitch of the row tiles: FFT scratch footprint plus one slot, so
@@ -1178,8 +1179,8 @@ hipError_t set_lds(F* fn, size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// rows per block: RB_COEF (capped by coef_rows) for the r2c pass over coefficient planes with at least that
-// many rows, else RB
+// rows per block: coef_rows for the r2c pass over coefficient planes with at least that many rows,
+// else cap_rows<M, RB>; the block's LDS also holds the FFT's twiddles
 template <int M, int TAG, int ROWS>
 hipError_t rows_r2c_rt(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
