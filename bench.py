@@ -92,11 +92,11 @@ def path_algorithmic_bytes(K: int, real_filters: bool) -> float:
     return B * (8 * N * M + 8 * K * N * M) + 2 * filt
 
 
-def traffic_from_profiles(kind: str, per_launch_units: float):
+def traffic_from_profiles(kind: str, per_launch_units: float, path: str = "", src: str = ""):
     """HBM bytes per launch measured with rocprofv3 counters (profiles/traffic.json), if the
     kernel source has not changed since; else None."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    src = os.path.join(ROOT, "paper_2006_04591_amd", "csrc", "kernels.hip")
+    path = path or os.path.join(ROOT, "profiles", "traffic.json")
+    src = src or os.path.join(ROOT, "paper_2006_04591_amd", "csrc", "kernels.hip")
     try:
         with open(path) as fh:
             rec = json.load(fh)
@@ -423,7 +423,8 @@ def copy_calibration(mib: int) -> int:
     return 0
 
 
-def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_csv: str, cal_bytes: int) -> int:
+def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_csv: str, cal_bytes: int,
+                    out_path: str = "", src: str = "") -> int:
     """Writes profiles/traffic.json: per-kernel HBM bytes per launch from rocprofv3 counter CSVs
     (FETCH_SIZE and WRITE_SIZE in KiB per dispatch), each scaled by the factor that makes the
     same counter read cal_bytes for the calibration copy kernel."""
@@ -461,12 +462,12 @@ def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_writ
         w = write.get(name, 0.0) * fw
         short = name.replace("(anonymous namespace)::", "").split("(")[0]
         out[kind] = {"kernel": short, "fetch_bytes": f, "write_bytes": w, "bytes_per_launch": f + w}
-    src = os.path.join(ROOT, "paper_2006_04591_amd", "csrc", "kernels.hip")
+    src = src or os.path.join(ROOT, "paper_2006_04591_amd", "csrc", "kernels.hip")
     with open(src, "rb") as fh:
         digest = hashlib.sha256(fh.read()).hexdigest()
     rec = {"kernels_hip_sha256": digest, "fetch_scale": ff, "write_scale": fw, "calibration_bytes": cal_bytes,
            "kernels": out}
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = out_path or os.path.join(ROOT, "profiles", "traffic.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
@@ -513,7 +514,7 @@ def main() -> int:
     if layer:
         B, N, M, J, SHEAR_LEVELS, CONFIG_ID = 32, 256, 256, 3, [1, 1, 2], 4
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); run with --gpus 1",
+        print(f"bench.py: measures one GPU only (got --gpus {args.gpus}); run with --gpus 1",
               file=sys.stderr)
         return 2
 
