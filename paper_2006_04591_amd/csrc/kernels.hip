@@ -578,8 +578,8 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(c
 
 // Row stage of one inpainting iteration (Algorithm 3): the rows of
 // u = mask (f_masked - f) + f, formed while loading, -> packed spectra.
-template <int M>
-__global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c_mix(const float* __restrict__ fm,
+template <int M, int ROWS>
+__global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_r2c_mix(const float* __restrict__ fm,
                                                                                 const float* __restrict__ mask,
                                                                                 const float* __restrict__ f,
                                                                                 float2* __restrict__ out, int N,
@@ -587,20 +587,20 @@ __global__ __launch_bounds__(RB*(M / 2) / Pts<M / 2>::value) void k_rows_r2c_mix
                                                                                 const float2* __restrict__ twM) {
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
-    const int nrb = N / RB;
+    const int nrb = N / ROWS;
     const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * RB;
+    const int row0 = (blockIdx.x % nrb) * ROWS;
     const size_t off = (size_t)plane * N * L;  // float2 units
     const float2* a = reinterpret_cast<const float2*>(fm) + off;
     const float2* m = reinterpret_cast<const float2*>(mask) + off;
     const float2* g = reinterpret_cast<const float2*>(f) + off;
-    row_r2c_tile_ld<M, Pts<L>::value, RB, true>(
-        [a, m, g](int row, int i) {
-            const size_t j = (size_t)row * L + i;
-            const float2 av = ld_stream(a + j), mv = ld_stream(m + j), gv = g[j];
-            return make_float2(mv.x * (av.x - gv.x) + gv.x, mv.y * (av.y - gv.y) + gv.y);
-        },
-        out + (size_t)plane * L * N, N, row0, lds, twL, twM, (int)threadIdx.x);
+    auto ld = [a, m, g](int row, int i) {
+        const size_t j = (size_t)row * L + i;
+        const float2 av = ld_stream(a + j), mv = ld_stream(m + j), gv = g[j];
+        return make_float2(mv.x * (av.x - gv.x) + gv.x, mv.y * (av.y - gv.y) + gv.y);
+    };
+    row_r2c_tile_ld<M, Pts<L>::value, ROWS, true, decltype(ld), true>(ld, out + (size_t)plane * L * N, N, row0, lds,
+                                                                      twL, twM, (int)threadIdx.x);
 }
 
 template <int M, int TAG, int ROWS>
@@ -1220,13 +1220,13 @@ hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes
 template <int M>
 hipError_t rows_r2c_mix_t(const DevPlan& d, const float* fm, const float* mask, const float* f, float2* out,
                           int planes, hipStream_t st) {
-    constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
-    const size_t lds = (size_t)RB * RowPitch<L, P>::value * sizeof(float2);
-    hipError_t e = set_lds(k_rows_r2c_mix<M>, lds);
+    constexpr int L = M / 2, P = Pts<L>::value, T = L / P, ROWS = cap_rows<M, RB>();
+    const size_t lds = ((size_t)ROWS * RowPitch<L, P>::value + L) * sizeof(float2);  // + the FFT twiddles
+    hipError_t e = set_lds(k_rows_r2c_mix<M, ROWS>, lds);
     if (e != hipSuccess) return e;
-    const size_t blocks = (size_t)planes * (d.N / RB);
-    hipLaunchKernelGGL((k_rows_r2c_mix<M>), dim3((unsigned)blocks), dim3(RB * T), lds, st, fm, mask, f, out, d.N,
-                       d.twL, d.twM);
+    const size_t blocks = (size_t)planes * (d.N / ROWS);
+    hipLaunchKernelGGL((k_rows_r2c_mix<M, ROWS>), dim3((unsigned)blocks), dim3(ROWS * T), lds, st, fm, mask, f, out,
+                       d.N, d.twL, d.twM);
     return hipGetLastError();
 }
 
