@@ -339,12 +339,36 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
 // A block loops over pixel tiles (stride gridDim.x) and writes its partial sums, and the bias
 // gradient sum_p dy[co](p), to part[blockIdx.x]; k_wgrad_reduce adds the partials in block order.
 // x: bf16 channel-last with CINP channels (the packed z, or a hidden activation).
+// Rows of the staged input tile have a pitch of XP = 40 bf16 (80 bytes): 16-byte aligned, so a
+// lane's 8 pixels at a tap's column offset come from two aligned 16-byte reads and a byte-align.
+constexpr int XP = 40;
+
+// bf16 elements off .. off + 7 (off in 0..2) of the 16 elements held in lo, hi
+__device__ __forceinline__ bf16x8 shifted8(uint4 lo, uint4 hi, int off) {
+    const unsigned d[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    union {
+        unsigned u[4];
+        bf16x8 v;
+    } r;
+    if (off == 0) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.u[j] = d[j];
+    } else if (off == 2) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.u[j] = d[j + 1];
+    } else {  // one element: each dword takes the high half of one and the low half of the next
+#pragma unroll
+        for (int j = 0; j < 4; ++j) r.u[j] = __builtin_amdgcn_alignbyte(d[j + 1], d[j], 2);
+    }
+    return r.v;
+}
+
 template <int CINP, int COUTP>
 __global__ __launch_bounds__(THREADS) void k_wgrad(WgradArgs a) {
     constexpr int MT = COUTP / 16, NTT = 9 * CINP / 16, TT = MT * NTT, TPW = (TT + 3) / 4;
     extern __shared__ unsigned short smem[];
     unsigned short* s_dy = smem;                      // [COUTP][TH][TW]
-    unsigned short* s_x = smem + COUTP * TH * TW;     // [CINP][HH][HW]
+    unsigned short* s_x = smem + COUTP * TH * TW;     // [CINP][HH][XP]
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lk = 8 * (l / 16);
     const int N = a.N, M = a.M;
@@ -366,7 +390,7 @@ __global__ __launch_bounds__(THREADS) void k_wgrad(WgradArgs a) {
         for (int i = threadIdx.x; i < CINP * HH * HW; i += THREADS) {
             const int xx = i % HW, r = i / HW, yy = r % HH, ci = r / HH;
             const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-            s_x[i] = a.xb[(((size_t)b * N + y) * M + x) * CINP + ci];
+            s_x[(ci * HH + yy) * XP + xx] = a.xb[(((size_t)b * N + y) * M + x) * CINP + ci];
         }
         __syncthreads();
         if (threadIdx.x < COUTP) {
@@ -383,14 +407,10 @@ __global__ __launch_bounds__(THREADS) void k_wgrad(WgradArgs a) {
                     const int tap = nt / (CINP / 16), cg = nt % (CINP / 16);
                     const int dy = tap / 3, dx = tap % 3;
                     const bf16x8 afr = *reinterpret_cast<const bf16x8*>(s_dy + ((mt * 16 + lr) * TH + r) * TW + lk);
-                    const unsigned short* xp = s_x + ((cg * 16 + lr) * HH + r + dy) * HW + lk + dx;
-                    union {
-                        unsigned short u[8];
-                        bf16x8 v;
-                    } bb;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) bb.u[q] = xp[q];
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bb.v, acc[j], 0, 0, 0);
+                    const uint4* xp =
+                        reinterpret_cast<const uint4*>(s_x + ((cg * 16 + lr) * HH + r + dy) * XP + lk);
+                    const bf16x8 bfr = shifted8(xp[0], xp[1], dx);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr, acc[j], 0, 0, 0);
                 }
             }
         }
@@ -496,7 +516,7 @@ hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
 template <int CINP, int COUTP>
 hipError_t wgrad_t(const WgradArgs& a, int blocks, hipStream_t st) {
     const void* fn = reinterpret_cast<const void*>(&k_wgrad<CINP, COUTP>);
-    const size_t lds = ((size_t)COUTP * TH * TW + (size_t)CINP * HH * HW) * 2;
+    const size_t lds = ((size_t)COUTP * TH * TW + (size_t)CINP * HH * XP) * 2;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
