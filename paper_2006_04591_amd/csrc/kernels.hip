@@ -269,8 +269,9 @@ struct Pts {
     static constexpr int value = (L >= 1024) ? 16 : (L == 256 ? 16 : 8);
 };
 
-constexpr int RB = 16;       // rows per block in the standalone row passes over images
-constexpr int RB_COEF = 32;  // ... over coefficient planes (when the plane has that many rows)
+constexpr int RB = 16;  // rows per block in the standalone row passes (32 measured slower once the twiddle
+                        // loads were off the tiles' critical path: 0.273 against 0.261 ms for the
+                        // coefficient r2c pass at 512 x 512 x 49 x 16)
 
 // rows per block of a standalone row pass: R, or fewer where that would exceed 512 threads (at
 // M = 1024 a 1024-thread block of 16 rows filled its CU alone, so the phases of one block could
@@ -279,11 +280,6 @@ template <int M, int R>
 constexpr int cap_rows() {
     constexpr int T = (M / 2) / Pts<M / 2>::value;
     return (R * T <= 512) ? R : 512 / T;
-}
-// ... of the coefficient row passes
-template <int M>
-constexpr int coef_rows() {
-    return cap_rows<M, RB_COEF>();
 }
 
 template <bool REAL>
@@ -1179,8 +1175,7 @@ hipError_t set_lds(F* fn, size_t bytes) {
     return hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-// rows per block: coef_rows for the r2c pass over coefficient planes with at least that many rows,
-// else cap_rows<M, RB>; the block's LDS also holds the FFT's twiddles
+// rows per block: cap_rows<M, RB>; the block's LDS also holds the FFT's twiddles
 template <int M, int TAG, int ROWS>
 hipError_t rows_r2c_rt(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
     constexpr int L = M / 2, P = Pts<L>::value, T = L / P;
@@ -1195,7 +1190,6 @@ hipError_t rows_r2c_rt(const DevPlan& d, const float* in, float2* out, int plane
 
 template <int M, int TAG>
 hipError_t rows_r2c_t(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
-    if (TAG == 1 && d.N >= coef_rows<M>()) return rows_r2c_rt<M, TAG, coef_rows<M>()>(d, in, out, planes, st);
     return rows_r2c_rt<M, TAG, cap_rows<M, RB>()>(d, in, out, planes, st);
 }
 
@@ -1246,7 +1240,6 @@ hipError_t rows_thresh_rt(const DevPlan& d, float2* planes, int nplanes, const f
 template <int M>
 hipError_t rows_thresh_t(const DevPlan& d, float2* planes, int nplanes, const float* thr, unsigned* kept,
                          hipStream_t st) {
-    if (d.N >= coef_rows<M>()) return rows_thresh_rt<M, coef_rows<M>()>(d, planes, nplanes, thr, kept, st);
     return rows_thresh_rt<M, cap_rows<M, RB>()>(d, planes, nplanes, thr, kept, st);
 }
 
