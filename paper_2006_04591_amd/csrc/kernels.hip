@@ -269,6 +269,13 @@ struct Pts {
     static constexpr int value = (L >= 1024) ? 16 : (L == 256 ? 16 : 8);
 };
 
+// points per thread of the column FFTs (N-point): 8 up to N = 512 (256-point columns use two
+// 32-thread groups per wavefront), 16 at N = 1024
+template <int N>
+struct ColPts {
+    static constexpr int value = (N >= 1024) ? 16 : 8;
+};
+
 constexpr int RB = 16;  // rows per block in the standalone row passes (32 measured slower once the twiddle
                         // loads were off the tiles' critical path: 0.273 against 0.261 ms for the
                         // coefficient r2c pass at 512 x 512 x 49 x 16)
@@ -731,7 +738,7 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_thres
 
 template <int N, int PW>
 struct ColCfg {
-    static constexpr int P = Pts<N>::value;
+    static constexpr int P = ColPts<N>::value;
     static constexpr int T = N / P;
     static constexpr int THREADS = PW * T;
     static constexpr size_t LDS = ((size_t)PW * ColScratch<N, P>::value + N) * sizeof(float2);
@@ -1413,7 +1420,7 @@ namespace {
 // FFT decompositions as the standalone kernels, so both paths round identically.
 template <int N, int M>
 struct FusedPick {
-    static constexpr int PC = Pts<N>::value;
+    static constexpr int PC = ColPts<N>::value;
     static constexpr int PW = 512 / (N / PC);
     static constexpr int PR = Pts<M / 2>::value;
     using C = FusedCfg<N, M, PC, PW, PR>;
