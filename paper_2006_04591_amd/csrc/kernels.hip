@@ -289,6 +289,25 @@ constexpr int cap_rows() {
     return (R * T <= 512) ? R : 512 / T;
 }
 
+// Logical block of a standalone row pass. Workgroups go to the 8 XCDs (each with its own L2) in
+// turn, so hardware blocks b, b + 8, b + 16, ... share an XCD and start together. Where a block
+// holds fewer than the 16 rows of a panel tile (S = 16 / ROWS blocks per tile), the S blocks of one
+// tile get such a set of hardware blocks, so that each 128-byte line of the tile is read and
+// written through one L2; a tail of fewer than 8 S blocks keeps its order.
+template <int ROWS>
+__device__ __forceinline__ int row_block() {
+    static_assert(ROWS >= 16 || 16 % ROWS == 0, "rows per block must divide the 16-row tile");
+    const int b = (int)blockIdx.x;
+    if constexpr (ROWS >= 16) {
+        return b;
+    } else {
+        constexpr int S = 16 / ROWS, G = 8 * S;
+        if (b >= (int)(gridDim.x / G) * G) return b;
+        const int w = b % G;
+        return b - w + (w % 8) * S + w / 8;
+    }
+}
+
 template <bool REAL>
 __device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, float2 a) {
     if constexpr (REAL) {
@@ -573,8 +592,9 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_r2c(c
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
     const int nrb = N / ROWS;
-    const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * ROWS;
+    const int blk = row_block<ROWS>();
+    const int plane = blk / nrb;
+    const int row0 = (blk % nrb) * ROWS;
     row_r2c_tile<M, Pts<L>::value, ROWS, true, true>(in + (size_t)plane * N * M, out + (size_t)plane * L * N, N, row0,
                                                      lds, twL, twM, (int)threadIdx.x);
 }
@@ -591,8 +611,9 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_r2c_m
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
     const int nrb = N / ROWS;
-    const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * ROWS;
+    const int blk = row_block<ROWS>();
+    const int plane = blk / nrb;
+    const int row0 = (blk % nrb) * ROWS;
     const size_t off = (size_t)plane * N * L;  // float2 units
     const float2* a = reinterpret_cast<const float2*>(fm) + off;
     const float2* m = reinterpret_cast<const float2*>(mask) + off;
@@ -615,8 +636,9 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_c2r(c
     constexpr int L = M / 2, P = Pts<L>::value;
     extern __shared__ float2 lds[];
     const int nrb = N / ROWS;
-    const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * ROWS;
+    const int blk = row_block<ROWS>();
+    const int plane = blk / nrb;
+    const int row0 = (blk % nrb) * ROWS;
     row_c2r_tile<M, P, ROWS, true, true>(in + (size_t)plane * L * N, out + (size_t)plane * N * M, N, row0, lds, twL,
                                          twM, scale, (int)threadIdx.x);
 }
@@ -730,8 +752,9 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_thres
     constexpr int L = M / 2;
     extern __shared__ float2 lds[];
     const int nrb = N / ROWS;
-    const int plane = blockIdx.x / nrb;
-    const int row0 = (blockIdx.x % nrb) * ROWS;
+    const int blk = row_block<ROWS>();
+    const int plane = blk / nrb;
+    const int row0 = (blk % nrb) * ROWS;
     row_thresh_tile<M, Pts<L>::value, ROWS>(planes + (size_t)plane * L * N, N, row0, lds, twL, twM, thr[plane],
                                           kept ? kept + plane : nullptr, (int)threadIdx.x);
 }
