@@ -38,6 +38,13 @@
  *   flight at a time: calls on different streams sharing a system race on its
  *   workspace.
  *
+ * Empty batches: shear_forward, shear_inverse, shear_adjoint, shear_denoise,
+ *   shear_inpaint and shear_shrink_apply with batch == 0 return SHEAR_OK at
+ *   once for a non-NULL system: nothing is launched and no other argument is
+ *   read (pointers may be NULL). A negative batch is SHEAR_E_INVALID; so is
+ *   batch == 0 for shear_reserve, shear_workspace_bytes, shear_autotune and
+ *   shear_shrink_train_step.
+ *
  * Errors: every int-returning call returns SHEAR_OK or a negative code; no
  * C++ exception crosses this boundary. shear_last_error() gives a message for
  * the most recent failure on the calling thread. Asynchronous kernel faults
@@ -53,7 +60,7 @@ extern "C" {
 #endif
 
 #define SHEAR_OK 0
-#define SHEAR_E_INVALID (-1) /* null pointer, non-positive batch or count, bad parameter */
+#define SHEAR_E_INVALID (-1) /* null pointer, negative batch, non-positive count, bad parameter */
 #define SHEAR_E_SIZE (-2)    /* size not supported, or a constructed kernel does not fit */
 #define SHEAR_E_FRAME (-3)   /* min W <= 1e-10 max W, or non-Hermitian spectra */
 #define SHEAR_E_NOMEM (-4)   /* device or host allocation failed / workspace cap too small */

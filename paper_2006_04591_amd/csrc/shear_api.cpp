@@ -357,8 +357,13 @@ int ensure_ws(shear_system* s, size_t bytes) {
     return SHEAR_OK;
 }
 
-int check_call(shear_system* s, const void* a, const void* b, int batch) {
+// check_call's result for an empty call (batch == 0 where allowed): the entry point returns
+// SHEAR_OK without launching or reading anything else
+constexpr int EMPTY_CALL = 1;
+
+int check_call(shear_system* s, const void* a, const void* b, int batch, bool allow_empty = false) {
     if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
+    if (batch == 0 && allow_empty) return EMPTY_CALL;
     if (!a || !b) return fail(SHEAR_E_INVALID, "input or output pointer is NULL");
     if (batch <= 0) return fail(SHEAR_E_INVALID, "batch must be positive");
     int dev = -1;
@@ -528,7 +533,8 @@ int inverse_pipeline(shear_system* s, const float* coeffs, float* x, int batch, 
 }
 
 int inverse_like(shear_system* s, const float* coeffs, float* x, int batch, void* stream, const void* filt) {
-    int rc = check_call(s, coeffs, x, batch);
+    int rc = check_call(s, coeffs, x, batch, true);
+    if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
     if (pipe_usable(s)) {
         s->abort_valid = false;
@@ -813,7 +819,8 @@ int shear_check(shear_system* s, void* hip_stream) {
 }
 
 int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, void* stream) {
-    int rc = check_call(s, x, coeffs, batch);
+    int rc = check_call(s, x, coeffs, batch, true);
+    if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
     if (pipe_usable(s)) {
         s->abort_valid = false;
@@ -888,7 +895,8 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
 
 int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
                   void* stream) {
-    int rc = check_call(s, x, y, batch);
+    int rc = check_call(s, x, y, batch, true);
+    if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
     if (!thresholds) return fail(SHEAR_E_INVALID, "thresholds pointer is NULL");
     int chunk = 0;
@@ -981,7 +989,8 @@ void drop_graph(shear_system* s) {
 
 int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, float* f, int batch,
                   const float* thresholds, int iterations, void* stream) {
-    int rc = check_call(s, f_masked, f, batch);
+    int rc = check_call(s, f_masked, f, batch, true);
+    if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
     if (!mask || !thresholds) return fail(SHEAR_E_INVALID, "mask or thresholds pointer is NULL");
     if (iterations < 1) return fail(SHEAR_E_INVALID, "iterations must be positive");
@@ -1306,7 +1315,8 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
 
 int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, float* tau, int batch, const float* sigma,
                        const void* packed, void* stream) {
-    int rc = check_call(s, coeffs, shrunk, batch);
+    int rc = check_call(s, coeffs, shrunk, batch, true);
+    if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
     if (!sigma || !packed) return fail(SHEAR_E_INVALID, "sigma or parameter pointer is NULL");
     if (!shear::shrink_supported(s->K, s->rows, s->cols))

@@ -4,6 +4,8 @@ Inputs are seeded and shared (synth); the oracle never sees a GPU output.
 Bar: relative L2 error <= 1e-5 (FP32 path vs FP64 oracle), also per plane
 normalised by ||x|| * RMS_k.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -226,6 +228,46 @@ def test_errors(gpu, lib):
         assert e.value.name == "SHEAR_E_NOMEM"
         with pytest.raises(ValueError):
             s.forward(_to(np.zeros((1, 16, 8)), gpu))
+
+
+def test_empty_and_negative_batches(cfg1, gpu, lib):
+    """batch == 0 is an empty call: SHEAR_OK, nothing launched, no pointer read (NULL is fine); a
+    negative batch is SHEAR_E_INVALID, as is batch == 0 where a size is being asked for (reserve,
+    workspace size). The binding turns empty tensors into empty results."""
+    from paper_2006_04591_amd import ShearError
+
+    s, ref, x = cfg1
+    _say("case: empty and negative batches")
+    xb = _to(x[None], gpu)
+    c_before = s.forward(xb)
+    torch.cuda.synchronize()
+    h = s._h
+    assert lib.shear_forward(h, None, None, 0, None) == 0
+    assert lib.shear_inverse(h, None, None, 0, None) == 0
+    assert lib.shear_adjoint(h, None, None, 0, None) == 0
+    assert lib.shear_denoise(h, None, None, 0, None, None, None) == 0
+    assert lib.shear_inpaint(h, None, None, None, 0, None, 0, None) == 0
+    assert lib.shear_shrink_apply(h, None, None, None, 0, None, None, None) == 0
+    xp, cp = ctypes.c_void_p(xb.data_ptr()), ctypes.c_void_p(c_before.data_ptr())
+    assert lib.shear_forward(h, xp, cp, -1, None) == -1
+    assert lib.shear_inverse(h, cp, xp, -1, None) == -1
+    assert lib.shear_forward(None, None, None, 0, None) == -1
+    for fn in (s.reserve, s.workspace_bytes):
+        with pytest.raises(ShearError) as e:
+            fn(0)
+        assert e.value.name == "SHEAR_E_INVALID"
+    e0 = torch.empty((0, 128, 128), dtype=torch.float32, device=gpu)
+    c = s.forward(e0)
+    assert tuple(c.shape) == (0, ref.K, 128, 128)
+    assert tuple(s.inverse(c).shape) == (0, 128, 128) and tuple(s.adjoint(c).shape) == (0, 128, 128)
+    y, kept = s.denoise(e0, s.paper_thresholds(20.0), kept=True)
+    assert tuple(y.shape) == (0, 128, 128) and tuple(kept.shape) == (0, ref.K)
+    f = s.inpaint(e0, e0, np.zeros((3, 0, ref.K), np.float32))
+    assert tuple(f.shape) == (0, 128, 128)
+    # the empty calls left the system as it was
+    c_after = s.forward(xb)
+    torch.cuda.synchronize()
+    assert torch.equal(c_before, c_after)
 
 
 # ---------------------------------------------------------------- full-size workloads, sampled against the oracle
