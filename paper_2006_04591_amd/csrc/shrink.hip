@@ -83,46 +83,87 @@ __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int 
     const int N = a.N, M = a.M;
     const uint4* in = reinterpret_cast<const uint4*>(a.in);
     constexpr int CH = CS / 8, CHI = CIN / 8;  // 16-byte chunks per staged / input pixel
-    for (int i = threadIdx.x; i < HH * HW * CH; i += THREADS) {
-        const int ch = i % CH, p = i / CH, xx = p % HW, yy = p / HW;
-        const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-        const uint4 v = in[(((size_t)b * N + y) * M + x) * CHI + cb / 8 + ch];
-        *reinterpret_cast<uint4*>(s + (yy * HW + xx) * PIX + ch * 8) = v;
+    constexpr int TOTAL = HH * HW * CH, NIT = (TOTAL + THREADS - 1) / THREADS;
+    // all of a thread's loads are issued before its first LDS store, so that they are in flight
+    // together (one load, wait and store at a time left each wavefront waiting on memory latency)
+    uint4 v[NIT];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
+        v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (i < TOTAL) {
+            const int ch = i % CH, p = i / CH, xx = p % HW, yy = p / HW;
+            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
+            v[j] = in[(((size_t)b * N + y) * M + x) * CHI + cb / 8 + ch];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
+        if (i < TOTAL) {
+            const int ch = i % CH, p = i / CH, xx = p % HW, yy = p / HW;
+            *reinterpret_cast<uint4*>(s + (yy * HW + xx) * PIX + ch * 8) = v[j];
+        }
     }
 }
 
 // Stages the halo tile of one image straight from the FP32 channel-first coefficient planes:
 // z = bf16(c x scale[b][k]) channel-last, zero beyond the a.cin real channels (the values
 // k_pack_z would write). The TW interior pixels of a tile row are read as aligned 16-byte
-// vectors, the two halo columns one value each.
+// vectors, the two halo columns one value each; as in stage, every load of a thread is issued
+// before its first LDS store.
 template <int CS>
 __device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0, int cb) {
     constexpr int PIX = Pix<CS>::value, QW = TW / 4;
+    constexpr int TOTAL = CS * HH * QW, NIT = (TOTAL + THREADS - 1) / THREADS;
+    constexpr int HTOTAL = CS * HH * 2, HNIT = (HTOTAL + THREADS - 1) / THREADS;
     const int N = a.N, M = a.M, K = a.cin;
-    for (int i = threadIdx.x; i < CS * HH * QW; i += THREADS) {
+    float4 v[NIT];
+    float sc[NIT], h[HNIT], hs[HNIT];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
         const int q = i % QW, yy = (i / QW) % HH, kl = i / (QW * HH), k = cb + kl;
-        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        float sc = 0.0f;
-        if (k < K) {
+        v[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        sc[j] = 0.0f;
+        if (i < TOTAL && k < K) {
             const int y = (y0 + yy - 1 + N) & (N - 1);
-            v = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
-            sc = a.scale[b * K + k];
+            v[j] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
+            sc[j] = a.scale[b * K + k];
         }
-        unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + kl;
-        d[0] = f2bf(v.x * sc);
-        d[PIX] = f2bf(v.y * sc);
-        d[2 * PIX] = f2bf(v.z * sc);
-        d[3 * PIX] = f2bf(v.w * sc);
     }
-    for (int i = threadIdx.x; i < CS * HH * 2; i += THREADS) {
+#pragma unroll
+    for (int j = 0; j < HNIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
         const int side = i % 2, yy = (i / 2) % HH, kl = i / (2 * HH), k = cb + kl;
         const int xx = side ? HW - 1 : 0;
-        float v = 0.0f;
-        if (k < K) {
+        h[j] = hs[j] = 0.0f;
+        if (i < HTOTAL && k < K) {
             const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-            v = a.coef[(((size_t)b * K + k) * N + y) * M + x] * a.scale[b * K + k];
+            h[j] = a.coef[(((size_t)b * K + k) * N + y) * M + x];
+            hs[j] = a.scale[b * K + k];
         }
-        s[(yy * HW + xx) * PIX + kl] = f2bf(v);
+    }
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
+        if (i < TOTAL) {
+            const int q = i % QW, yy = (i / QW) % HH, kl = i / (QW * HH);
+            unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + kl;
+            d[0] = f2bf(v[j].x * sc[j]);
+            d[PIX] = f2bf(v[j].y * sc[j]);
+            d[2 * PIX] = f2bf(v[j].z * sc[j]);
+            d[3 * PIX] = f2bf(v[j].w * sc[j]);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < HNIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
+        if (i < HTOTAL) {
+            const int side = i % 2, yy = (i / 2) % HH, kl = i / (2 * HH);
+            const int xx = side ? HW - 1 : 0;
+            s[(yy * HW + xx) * PIX + kl] = f2bf(h[j] * hs[j]);
+        }
     }
 }
 
