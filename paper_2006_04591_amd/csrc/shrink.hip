@@ -273,6 +273,27 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         static_assert(COUTP % CG == 0, "the passes cover the padded output channels exactly");
 #pragma unroll 1
         for (int c0 = 0; c0 < COUTP; c0 += CG) {
+        // the pass's coefficient vectors, bias and scale are loaded before its products, so that
+        // their latency overlaps the matrix work (loaded after the stores of the previous vector,
+        // each load would also wait for those stores: one memory counter covers both)
+        float4 cvs[NG][4];
+        float biass[NG], scs[NG];
+#pragma unroll
+        for (int nt = 0; nt < NG; ++nt) {
+            const int k = c0 + nt * 16 + lr;
+            biass[nt] = scs[nt] = 0.0f;
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) cvs[nt][mt] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (k < a.cout) {
+                biass[nt] = a.bias[k];
+                scs[nt] = a.scale[b * a.cout + k];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
+                    cvs[nt][mt] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * a.cout + k) * a.N + y) * a.M + x);
+                }
+            }
+        }
         f32x4 acc[4][NG];
         zero_acc(acc);
         mma<CINP, CS, CG>(a, s_in, acc, c0, 0);
@@ -280,14 +301,14 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         for (int nt = 0; nt < NG; ++nt) {
             const int k = c0 + nt * 16 + lr;
             if (k >= a.cout) continue;
-            const float bias = a.bias[k];
-            const float sc = a.scale[b * a.cout + k];
+            const float bias = biass[nt];
+            const float sc = scs[nt];
             const bool lowpass = (k == a.lowpass);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
                 const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
                 const size_t off = (((size_t)b * a.cout + k) * a.N + y) * a.M + x;
-                const float4 cv = *reinterpret_cast<const float4*>(a.coef + off);
+                const float4 cv = cvs[nt][mt];
                 const float v[4] = {cv.x, cv.y, cv.z, cv.w};
                 float t[4], r[4];
 #pragma unroll
