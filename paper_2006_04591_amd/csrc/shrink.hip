@@ -203,32 +203,52 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[4][NT]) {
 // out[pixel][co] accumulators of a wavefront: 4 m-tiles (16 pixels of one row) x NT n-tiles, added
 // to acc: output channels co0 .. co0 + COUTP - 1 of the packed weights (CINP input channels per
 // tap), input channels cb .. cb + CS - 1 staged in s.
-template <int CINP, int CS, int COUTP>
+template <int CINP, int CS, int COUTP, bool PIPE = true>
 __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, f32x4 (&acc)[4][COUTP / 16], int co0,
                                     int cb) {
     constexpr int PIX = Pix<CS>::value, NT = COUTP / 16;
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lk = 8 * (l / 16);
     const unsigned short* W = a.W;
-#pragma unroll 1
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3, dx = tap % 3;
+    // steps (tap, 32-channel chunk kc) in order. PIPE: the weight fragments of the next step are
+    // loaded before the current step's products, so that their latency overlaps them (NT x 4 more
+    // VGPRs; the shrink epilogue's kernel loses a wave per SIMD to them and runs slower)
+    constexpr int KCN = CS / 32, STEPS = 9 * KCN;
+    auto wfrag = [&](int it, int nt) {
+        const int tap = it / KCN, kc = it % KCN;
+        return *reinterpret_cast<const bf16x8*>(W + ((size_t)(co0 + nt * 16 + lr) * 9 + tap) * CINP + cb + kc * 32 +
+                                                lk);
+    };
+    bf16x8 bfr[NT];
+    if constexpr (PIPE) {
 #pragma unroll
-        for (int kc = 0; kc < CS / 32; ++kc) {
-            bf16x8 bfr[NT];
+        for (int nt = 0; nt < NT; ++nt) bfr[nt] = wfrag(0, nt);
+    }
+#pragma unroll 1
+    for (int it = 0; it < STEPS; ++it) {
+        const int tap = it / KCN, kc = it % KCN, dy = tap / 3, dx = tap % 3;
+        const int nx = (it + 1 < STEPS) ? it + 1 : it;  // the last step re-loads its own fragments
+        bf16x8 bnx[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if constexpr (PIPE) {
+                bnx[nt] = wfrag(nx, nt);
+            } else {
+                bfr[nt] = wfrag(it, nt);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int row = 2 * w + mt / 2, xs = (mt % 2) * 16;
+            const bf16x8 afr =
+                *reinterpret_cast<const bf16x8*>(s + ((row + dy) * HW + xs + lr + dx) * PIX + kc * 32 + lk);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                bfr[nt] = *reinterpret_cast<const bf16x8*>(W + ((size_t)(co0 + nt * 16 + lr) * 9 + tap) * CINP +
-                                                           cb + kc * 32 + lk);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[nt], acc[mt][nt], 0, 0, 0);
+        }
+        if constexpr (PIPE) {
 #pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int row = 2 * w + mt / 2, xs = (mt % 2) * 16;
-                const bf16x8 afr =
-                    *reinterpret_cast<const bf16x8*>(s + ((row + dy) * HW + xs + lr + dx) * PIX + kc * 32 + lk);
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[nt], acc[mt][nt], 0, 0, 0);
-            }
+            for (int nt = 0; nt < NT; ++nt) bfr[nt] = bnx[nt];
         }
     }
 }
@@ -296,7 +316,7 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         }
         f32x4 acc[4][NG];
         zero_acc(acc);
-        mma<CINP, CS, CG>(a, s_in, acc, c0, 0);
+        mma<CINP, CS, CG, false>(a, s_in, acc, c0, 0);
 #pragma unroll
         for (int nt = 0; nt < NG; ++nt) {
             const int k = c0 + nt * 16 + lr;
