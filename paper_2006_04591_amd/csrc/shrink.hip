@@ -62,14 +62,18 @@ struct Pix {
 // padded gradient planes of layer 2's training epilogue) reuses it once the products are done.
 // The shrink epilogue (MODE 2) works from registers.
 // Input channels are staged at most 32 at a time (a layer with 64 input channels stages and
-// multiplies twice), which keeps the tile at 27 KB.
-template <int CINP>
+// multiplies twice), which keeps the tile at 27 KB; the layer that stages from the coefficient
+// planes (COEF_IN) stages all of them at once (49 KB at 64 channels: its registers already hold
+// it to 3 blocks per CU, and one stage-and-multiply phase instead of two saves a barrier and
+// lets the second half's loads start without waiting for the first half's products).
+template <int CINP, bool COEF_IN = false>
 constexpr int staged_ch() {
-    return CINP > 32 ? 32 : CINP;
+    return (CINP > 32 && !COEF_IN) ? 32 : CINP;
 }
-template <int CINP, int OUTC, int MODE>
+template <int CINP, int OUTC, int MODE, bool COEF_IN = false>
 constexpr size_t conv_lds_bytes() {
-    constexpr size_t in = (size_t)HH * HW * Pix<staged_ch<CINP>()>::value * 2, out = (size_t)TH * TW * OUTC * 2;
+    constexpr size_t in = (size_t)HH * HW * Pix<staged_ch<CINP, COEF_IN>()>::value * 2,
+                     out = (size_t)TH * TW * OUTC * 2;
     return (MODE == 2 || in >= out) ? in : out;
 }
 
@@ -110,28 +114,18 @@ __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int 
 // Stages the halo tile of one image straight from the FP32 channel-first coefficient planes:
 // z = bf16(c x scale[b][k]) channel-last, zero beyond the a.cin real channels (the values
 // k_pack_z would write). The TW interior pixels of a tile row are read as aligned 16-byte
-// vectors, the two halo columns one value each; as in stage, every load of a thread is issued
-// before its first LDS store.
+// vectors, the two halo columns one value each. The halo loads come first, then the interior in
+// batches of up to 32 channels; as in stage, a batch's loads are all issued before its first
+// LDS store.
 template <int CS>
 __device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0, int cb) {
     constexpr int PIX = Pix<CS>::value, QW = TW / 4;
-    constexpr int TOTAL = CS * HH * QW, NIT = (TOTAL + THREADS - 1) / THREADS;
+    constexpr int SB = CS < 32 ? CS : 32;  // channels per batch of loads (registers)
+    static_assert(CS % SB == 0, "whole batches");
+    constexpr int TOTAL = SB * HH * QW, NIT = (TOTAL + THREADS - 1) / THREADS;
     constexpr int HTOTAL = CS * HH * 2, HNIT = (HTOTAL + THREADS - 1) / THREADS;
     const int N = a.N, M = a.M, K = a.cin;
-    float4 v[NIT];
-    float sc[NIT], h[HNIT], hs[HNIT];
-#pragma unroll
-    for (int j = 0; j < NIT; ++j) {
-        const int i = (int)threadIdx.x + j * THREADS;
-        const int q = i % QW, yy = (i / QW) % HH, kl = i / (QW * HH), k = cb + kl;
-        v[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        sc[j] = 0.0f;
-        if (i < TOTAL && k < K) {
-            const int y = (y0 + yy - 1 + N) & (N - 1);
-            v[j] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
-            sc[j] = a.scale[b * K + k];
-        }
-    }
+    float h[HNIT], hs[HNIT];
 #pragma unroll
     for (int j = 0; j < HNIT; ++j) {
         const int i = (int)threadIdx.x + j * THREADS;
@@ -144,16 +138,33 @@ __device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s,
             hs[j] = a.scale[b * K + k];
         }
     }
+#pragma unroll 1
+    for (int sb = 0; sb < CS; sb += SB) {
+        float4 v[NIT];
+        float sc[NIT];
 #pragma unroll
-    for (int j = 0; j < NIT; ++j) {
-        const int i = (int)threadIdx.x + j * THREADS;
-        if (i < TOTAL) {
-            const int q = i % QW, yy = (i / QW) % HH, kl = i / (QW * HH);
-            unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + kl;
-            d[0] = f2bf(v[j].x * sc[j]);
-            d[PIX] = f2bf(v[j].y * sc[j]);
-            d[2 * PIX] = f2bf(v[j].z * sc[j]);
-            d[3 * PIX] = f2bf(v[j].w * sc[j]);
+        for (int j = 0; j < NIT; ++j) {
+            const int i = (int)threadIdx.x + j * THREADS;
+            const int q = i % QW, yy = (i / QW) % HH, kl = sb + i / (QW * HH), k = cb + kl;
+            v[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            sc[j] = 0.0f;
+            if (i < TOTAL && k < K) {
+                const int y = (y0 + yy - 1 + N) & (N - 1);
+                v[j] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
+                sc[j] = a.scale[b * K + k];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NIT; ++j) {
+            const int i = (int)threadIdx.x + j * THREADS;
+            if (i < TOTAL) {
+                const int q = i % QW, yy = (i / QW) % HH, kl = sb + i / (QW * HH);
+                unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + kl;
+                d[0] = f2bf(v[j].x * sc[j]);
+                d[PIX] = f2bf(v[j].y * sc[j]);
+                d[2 * PIX] = f2bf(v[j].z * sc[j]);
+                d[3 * PIX] = f2bf(v[j].w * sc[j]);
+            }
         }
     }
 #pragma unroll
@@ -268,7 +279,7 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
     const int tx = a.M / TW, ty = a.N / TH;
     const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, b = blockIdx.x / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
-    constexpr int CS = staged_ch<CINP>();
+    constexpr int CS = staged_ch<CINP, COEF_IN>();
     static_assert(MODE != 2 || CS == CINP, "the shrink layer stages its whole input once");
     auto stage_part = [&](int cb) {
         if constexpr (COEF_IN) {
@@ -584,7 +595,7 @@ __global__ void k_pack_bias(const float* __restrict__ b, float* __restrict__ out
 template <int CINP, int COUTP, int MODE, int OUTC = 32, bool COEF_IN = false>
 hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
     const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC, COEF_IN>);
-    const size_t lds = conv_lds_bytes<CINP, OUTC, MODE>();
+    const size_t lds = conv_lds_bytes<CINP, OUTC, MODE, COEF_IN>();
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
