@@ -1235,7 +1235,6 @@ hipError_t rows_c2r_rt(const DevPlan& d, const float2* in, float* out, int plane
     return hipGetLastError();
 }
 
-// (the c2r passes measured faster with 16-row tiles, the coefficient r2c pass with 32)
 template <int M, int TAG>
 hipError_t rows_c2r_t(const DevPlan& d, const float2* in, float* out, int planes, float scale, hipStream_t st) {
     return rows_c2r_rt<M, TAG, cap_rows<M, RB>()>(d, in, out, planes, scale, st);

@@ -178,8 +178,14 @@ def test_denoise_errors(sys128, gpu):
     assert rc == -1
     with pytest.raises(ValueError):
         s.denoise(x, np.zeros(s.K + 1, np.float32))
+    # an empty batch is a successful no-op, a negative one is invalid
+    assert tuple(s.denoise(x[:0], np.zeros(s.K, np.float32)).shape) == (0, 128, 128)
+    thr = torch.zeros((1, s.K), dtype=torch.float32, device=gpu)
+    rc = lib.shear_denoise(s._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), -1,
+                           ctypes.c_void_p(thr.data_ptr()), None, None)
+    assert rc == -1
     with pytest.raises(ShearError):
-        s.denoise(x[:0], np.zeros(s.K, np.float32))
+        s.reserve(-1)
 
 
 def test_denoise_config2_sampled(gpu):
