@@ -1401,7 +1401,10 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
     return hipErrorInvalidValue;
 }
 
-#define SHEAR_COLS_SWITCH(PWSEL, FN, ...)                                          \
+// PW8_1024: the block width that serves 8-column panels at N = 1024 (4 for the forward pass:
+// two 256-thread blocks per CU instead of one of 512 at the same register-bound occupancy,
+// 0.22 -> 0.20 ms in the uneven inpainting; the inverse stays at 8, which measured faster there)
+#define SHEAR_COLS_SWITCH(PWSEL, PW8_1024, FN, ...)                                \
     if (d.L >= 16 && (PWSEL) == 16) {                                              \
         switch (d.N) {                                                             \
             case 16: return FN<16, 16>(__VA_ARGS__);                               \
@@ -1420,19 +1423,19 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
             case 128: return FN<128, 8>(__VA_ARGS__);                              \
             case 256: return FN<256, 8>(__VA_ARGS__);                              \
             case 512: return FN<512, 8>(__VA_ARGS__);                              \
-            case 1024: return FN<1024, 8>(__VA_ARGS__);                            \
+            case 1024: return FN<1024, PW8_1024>(__VA_ARGS__);                     \
         }                                                                          \
     }                                                                              \
     return hipErrorInvalidValue;
 
 hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
                            hipStream_t st) {
-    SHEAR_COLS_SWITCH(d.pw_fwd, cols_fwd_t, d, A, T, nimg, filt, scale, st)
+    SHEAR_COLS_SWITCH(d.pw_fwd, 4, cols_fwd_t, d, A, T, nimg, filt, scale, st)
 }
 
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
                            hipStream_t st) {
-    SHEAR_COLS_SWITCH(d.pw_inv, cols_inv_t, d, U, V, nimg, filt, part, st)
+    SHEAR_COLS_SWITCH(d.pw_inv, 8, cols_inv_t, d, U, V, nimg, filt, part, st)
 }
 
 // ---------------------------------------------------------------- fused dispatch
