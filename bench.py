@@ -485,10 +485,6 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle baseline sample length (0 = skip)")
-    ap.add_argument("--path", default="separate", choices=("pipeline", "separate", "persistent"),
-                    help="execution path of the transform calls")
-    ap.add_argument("--chunk", type=int, default=0, help="pipeline: images per chunk (0 = library default)")
-    ap.add_argument("--fpb", type=int, default=0, help="pipeline: filters per column block (0 = library default)")
     ap.add_argument("--chunk-images", type=int, default=0,
                     help="images per chunk of the K-expanded intermediate (0 = whole batch)")
     ap.add_argument("--train-steps", type=int, default=1250, help="shrink: training steps (16 pairs each)")
@@ -535,7 +531,6 @@ def main() -> int:
         pb = N * (M // 2) * 8
         cap = B * pb + args.chunk_images * 49 * pb
     shs = ShearletSystem.build(N, M, J, max_workspace_bytes=cap)
-    shs.set_path(args.path, args.chunk, args.fpb)
     build_s = time.perf_counter() - t0
     K = shs.K
     S, _ = shs.export_spectra()
@@ -595,7 +590,6 @@ def main() -> int:
     per_step = np.array([evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)])
     rec = shs.profile_read()
     shs.profile(False)
-    shs.check()
     ms_step = ms_total / args.steps
     log(f"bench: {args.steps} timed steps, {ms_step:.3f} ms/step")
 
@@ -688,12 +682,6 @@ def main() -> int:
         out["config"]["path"] = "separate (fused row threshold kernel)"
     elif not layer:
         out["reconstruction_rel_err"] = err
-    if not denoise:
-        out["config"]["path"] = args.path
-    if args.chunk:
-        out["config"]["pipeline_chunk_images"] = args.chunk
-    if args.fpb:
-        out["config"]["pipeline_filters_per_block"] = args.fpb
     if args.chunk_images > 0:
         out["config"]["chunk_images"] = args.chunk_images
     if args.cpu_seconds > 0:

@@ -140,8 +140,7 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
  * kept: batch*K uint32 (device) or NULL; if given, it is cleared and receives
  * the number of coefficients kept per plane. The thresholded coefficients are
  * never written to memory: the threshold sits between the forward row stage
- * and the inverse row stage of one kernel. Always runs the separate-launch
- * kernels, whatever shear_set_path selected. Asynchronous. */
+ * and the inverse row stage of one kernel. Asynchronous. */
 int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
                   void* hip_stream);
 
@@ -158,7 +157,6 @@ int shear_denoise(shear_system* s, const float* x, float* y, int batch, const fl
  * workspace change) and replayed on hip_stream; with per-launch timing on
  * (shear_profile_enable) the launches are issued directly instead. The
  * combination mask (f_masked - f) + f is formed inside the row-FFT kernel.
- * Runs the separate-launch kernels whatever shear_set_path selected.
  * Asynchronous. */
 int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, float* f, int batch,
                   const float* thresholds, int iterations, void* hip_stream);
@@ -223,13 +221,8 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
 #define SHEAR_KERNEL_ROWS_R2C_COEFFS 3 /* inverse/adjoint: row FFT of the coefficient planes */
 #define SHEAR_KERNEL_COLS_INV 4        /* inverse/adjoint: column FFT, x filter, sum over k, IFFT */
 #define SHEAR_KERNEL_ROWS_C2R_IMAGES 5 /* inverse/adjoint: row inverse FFT -> images   */
-#define SHEAR_KERNEL_FUSED_FWD 6       /* forward, fused path: kinds 1 + 2 in one persistent kernel */
-#define SHEAR_KERNEL_FUSED_INV 7       /* inverse/adjoint, fused path: kinds 3 + 4 in one persistent kernel */
-#define SHEAR_KERNEL_PIPE_FWD 8        /* forward, pipeline path: one chunk step (column + row stages) */
-#define SHEAR_KERNEL_PIPE_INV 9        /* inverse/adjoint, pipeline path: one chunk step */
-#define SHEAR_KERNEL_PIPE_FINISH 10    /* inverse/adjoint, pipeline path: sum of partial spectra + column IFFT */
-#define SHEAR_KERNEL_ROWS_THRESH 11    /* denoising: row inverse FFT, hard threshold, row FFT (in place) */
-#define SHEAR_KERNEL_KINDS 12
+#define SHEAR_KERNEL_ROWS_THRESH 6     /* denoising: row inverse FFT, hard threshold, row FFT (in place) */
+#define SHEAR_KERNEL_KINDS 7
 
 /* Per-launch timing (tracing). While enabled, every kernel launch of the
  * system is bracketed by two hipEvents recorded on the caller's stream. */
@@ -239,33 +232,6 @@ int shear_profile_enable(shear_system* s, int on);
  * and their summed duration in ms (arrays of SHEAR_KERNEL_KINDS) since the
  * previous read, and clears the record. */
 int shear_profile_read(shear_system* s, int* launches, double* total_ms);
-
-/* Execution paths of the transform calls. All give the same results up to
- * floating-point rounding; all paths use identical per-element operations and
- * agree bitwise in the forward direction.
- *   SHEAR_PATH_SEPARATE (default): one launch per stage over the whole batch
- *     (or workspace-limited chunks) through a batch-sized intermediate; all sizes.
- *   SHEAR_PATH_PIPELINE (rows, cols in {128, 256, 512, 1024}):
- *     the batch is processed in chunks of images; each launch runs the
- *     column stage of one chunk together with the coefficient row stage of
- *     the neighbouring chunk, exchanging planes through two buffers of
- *     chunk_images * K planes that stay in the on-package cache.
- *   SHEAR_PATH_PERSISTENT (rows, cols in {128, 256, 512, 1024}): one
- *     cooperative persistent kernel per direction fuses the column stage and
- *     the coefficient row stage; planes pass between them through a ring of
- *     exchange slots held in the L2 of one XCD (blocks take work only from the
- *     queue of the XCD they run on), with counter-based waits inside the XCD. */
-#define SHEAR_PATH_PIPELINE 0
-#define SHEAR_PATH_SEPARATE 1
-#define SHEAR_PATH_PERSISTENT 2
-
-/* Selects the path of later transform calls. For SHEAR_PATH_PIPELINE,
- * chunk_images (> 0) sets the chunk and filters_per_block (> 0) the filters
- * one column block processes. For SHEAR_PATH_PERSISTENT, chunk_images (> 0)
- * sets the images an XCD transforms at once and filters_per_block (> 0) the
- * exchange slots per image. 0 keeps the current value. SHEAR_E_SIZE if the
- * path does not support the system's size. */
-int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_block);
 
 /* Column-pass schedule of the separate-launch kernels: pw_fwd / pw_inv
  * columns per block (16 or 8; 16 needs cols >= 32) and kg_fwd / kg_inv
@@ -289,11 +255,6 @@ int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int 
  * allocates the workspace for batch if needed, uses the null stream. Drops
  * any captured inpainting graph. */
 int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv);
-
-/* Waits for hip_stream, then reports SHEAR_E_HIP if the last fused launch of
- * the system gave up on a dependency wait (its output is then invalid). The
- * fused kernels bound every wait, so they always terminate. */
-int shear_check(shear_system* s, void* hip_stream);
 
 /* Frees a system. The caller must have synchronised every stream that used it. */
 void shear_destroy_system(shear_system* s);

@@ -39,7 +39,6 @@ EXPORTED = (
     "shear_inpaint",
     "shear_profile_enable",
     "shear_profile_read",
-    "shear_set_path",
     "shear_set_schedule",
     "shear_autotune",
     "shear_shrink_params_bytes",
@@ -47,7 +46,6 @@ EXPORTED = (
     "shear_shrink_apply",
     "shear_shrink_param_count",
     "shear_shrink_train_step",
-    "shear_check",
     "shear_destroy_system",
     "shear_strerror",
     "shear_last_error",
@@ -107,7 +105,6 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     for name in EXPORTED:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
-    lib.shear_set_path.argtypes = [P, I, I, I]
     lib.shear_set_schedule.argtypes = [P, I, I, I, I]
     lib.shear_shrink_params_bytes.argtypes = [I, ctypes.POINTER(ctypes.c_size_t)]
     lib.shear_shrink_pack.argtypes = [P, P, P, P, P, P, P, P, P]
@@ -115,7 +112,6 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shear_shrink_param_count.argtypes = [I]
     lib.shear_shrink_train_step.argtypes = [P, P, P, I, P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, P, P]
     lib.shear_autotune.argtypes = [P, I, pI, pI, pI, pI]
-    lib.shear_check.argtypes = [P, P]
     lib.shear_profile_enable.argtypes = [P, I]
     lib.shear_profile_read.argtypes = [P, pI, pD]
     lib.shear_destroy_system.argtypes = [P]
@@ -358,14 +354,7 @@ class ShearletSystem:
         self._keep = thr
         return out
 
-    # ------------------------------------------------------------ execution path
-    PATHS = {"pipeline": 0, "separate": 1, "persistent": 2}
-
-    def set_path(self, path: str, chunk_images: int = 0, filters_per_block: int = 0) -> None:
-        """Execution path: "separate" (default), "pipeline" or "persistent" (shear_set_path)."""
-        _check(self._lib.shear_set_path(self._h, self.PATHS[path], int(chunk_images), int(filters_per_block)),
-               "shear_set_path")
-
+    # ------------------------------------------------------------ column-pass schedule
     def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0, kg_fwd: int = 0, kg_inv: int = 0) -> None:
         """Columns per block and filter groups of the forward and inverse column passes (shear_set_schedule);
         0 keeps a value."""
@@ -379,13 +368,9 @@ class ShearletSystem:
         _check(self._lib.shear_autotune(self._h, int(batch), *[ctypes.byref(x) for x in v]), "shear_autotune")
         return tuple(x.value for x in v)
 
-    def check(self, stream=None) -> None:
-        """Waits for the stream and raises if the last fused launch gave up on a dependency (shear_check)."""
-        _check(self._lib.shear_check(self._h, _stream_ptr(stream)), "shear_check")
-
     # ------------------------------------------------------------ tracing
     KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images",
-                    "fused_fwd", "fused_inv", "pipe_fwd", "pipe_inv", "pipe_finish", "rows_thresh")
+                    "rows_thresh")
 
     def profile(self, on: bool = True) -> None:
         """Brackets every launch with hipEvents on the caller's stream (shear_profile_enable)."""

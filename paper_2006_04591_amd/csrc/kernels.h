@@ -64,80 +64,7 @@ hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nim
 
 bool size_supported(int n);
 
-// ---------------------------------------------------------------- fused persistent path
-
-struct FusedGeom {
-    int B, K, L, N;     // batch, filters, packed columns, rows
-    int GI, S, Qmax;    // images per group, ring slots per image, queues (XCDs) the slots are sized for
-    int npan, nrb;      // column panels and row tiles per plane
-};
-
-// Counter words of a fused launch (zeroed before it): census, arrival, abort
-// flag, queue heads, and two per exchange slot.
-constexpr int kFusedMaxXcc = 16;
-inline size_t fused_ctr_words(const FusedGeom& g) { return 2 * kFusedMaxXcc + 2 + 2 * (size_t)g.Qmax * g.GI * g.S; }
-inline size_t fused_abort_word() { return kFusedMaxXcc + 1; }
-
-struct FusedBufs {
-    const float2* A;   // forward: unscaled row spectra of the images (B x L x N)
-    const float* cin;  // inverse: coefficients (B x K x N x M)
-    float* cout;       // forward: coefficients
-    float2* V;         // inverse: accumulated spectra (B x L x N)
-    float2* slots;     // Qmax * GI * S exchange planes of L x N
-    unsigned* ctr;     // fused_ctr_words(g) counters
-    const void* filt;
-    const float2* twN;
-    const float2* twL;
-    const float2* twM;
-    float scale;
-};
-
-struct FusedInfo {
-    const void* fn = nullptr;
-    int threads = 0;
-    size_t lds = 0;
-    int npan = 0, nrb = 0;
-    int blocks_per_cu = 0;
-};
-
-bool fused_supported(int N, int M);
-// Kernel, block shape, tiles per plane and occupancy of the fused kernel of one direction.
-hipError_t fused_info(const DevPlan& d, bool fwd, FusedInfo& fi);
-// Cooperative launch (all blocks co-resident) of grid blocks.
-hipError_t launch_fused(const FusedInfo& fi, const FusedGeom& g, const FusedBufs& bf, int grid, hipStream_t st);
+// Fills n words with zero (a kernel, so that the fill can be captured in a graph).
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
-
-// ---------------------------------------------------------------- skewed pipeline path
-
-struct SkewArgs {
-    int K, L, N;
-    int npan, nrb;      // column panels and row tiles per plane
-    int kper, kg;       // filters per column block, filter groups (kg = ceil(K / kper))
-    int col_b0, col_nb; // images of the column stage of this launch
-    int row_b0, row_nb; // images of the row stage of this launch
-    const float2* A;    // forward: unscaled row spectra of the images (B x L x N)
-    float* cout;        // forward: coefficients (B x K x N x M)
-    const float* cin;   // inverse: coefficients
-    float2* bufC;       // exchange buffer of the column stage (images of the chunk x K planes)
-    float2* bufR;       // exchange buffer of the row stage
-    float2* part;       // inverse: partial spectra (B x kg x L x N)
-    float2* part0;      // inverse: partial mirrored-term columns (B x kg x N)
-    float2* V;          // inverse: summed spectra after the column IFFT (B x L x N)
-    const void* filt;
-    const float2* twN;
-    const float2* twL;
-    const float2* twM;
-    float scale;
-};
-
-struct SkewTiles {
-    bool ok = false;
-    int npan = 0, nrb = 0;
-};
-
-// Tiles per plane of the pipeline kernels (rows, cols in {128, 256, 512, 1024}).
-SkewTiles skew_tiles(const DevPlan& d);
-// which: 0 forward step, 1 inverse step, 2 inverse finish (blocks = B * npan).
-hipError_t launch_skew(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st);
 
 }  // namespace shear

@@ -858,341 +858,6 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv_finish(co
     col_inv_finish<N, P, PW>(acc, pan * PW, V + (size_t)b * L * N, lds, twN, tid);
 }
 
-// ---------------------------------------------------------------- XCD-local persistent kernels
-// One cooperative launch per transform direction fuses the column stage and
-// the coefficient row stage, and hands each (image, filter) plane from one
-// stage to the other through a small ring of exchange slots that stays in the
-// L2 of one XCD. The L2 is the coherence point of the compute units of an XCD
-// but not across XCDs, so every slot is produced and consumed by blocks of one
-// XCD: each block reads the id of the XCD it runs on (hardware register
-// XCC_ID), and takes work only from that XCD's queue.
-//
-// Start-up census: every block counts itself on its XCD and on a launch-wide
-// arrival counter, then waits until all blocks of the (co-resident) grid have
-// arrived. The XCDs that hold blocks, in id order, are the queues; image b goes
-// to queue b mod Q.
-//
-// Tasks of a queue, in dequeue order, per group of GI images: the GI x npan
-// column tasks (one panel of PW columns of one image, looping over all K
-// filters), then the K x GI x nrb row tasks (ROWS rows of one plane), filter
-// major. Image i of a group uses the slots i*S .. i*S+S-1 of its queue, filter
-// k the slot k mod S; a slot's uses are numbered across the groups
-// (generation), and each slot counts the column and the row tasks that have
-// finished with it.
-//
-// Ordering within an XCD: a finishing task waits for its own loads and stores
-// (stores are acknowledged by the L2), passes a block barrier, and one thread
-// adds to the slot's counter with a relaxed atomic. A waiting task polls the
-// counter with relaxed atomic loads, invalidates its compute unit's L1 with an
-// acquire fence, and passes a block barrier. No L2 write-back is needed
-// because producer and consumer share the L2; kernel boundaries order
-// everything else (inputs, outputs, counters).
-//
-// Progress: a task waits only on tasks dequeued before it, except the column
-// tasks of a group, which wait on the row tasks after them; their number
-// (GI x npan) must stay below the blocks of the queue, which the census
-// checks. Every wait is bounded: on timeout it raises an abort flag that makes
-// every other wait give up, so the kernel always drains; the host reports the
-// flag through shear_check.
-
-constexpr int SPIN_LIMIT = 1 << 18;
-constexpr int kMaxXcc = 16;  // XCC_ID values are taken modulo this
-
-// counter words of a launch: census, arrival, abort flag, queue heads, then
-// two counters (column side, row side) per slot
-constexpr int CTR_CENSUS = 0;
-constexpr int CTR_ARRIVED = kMaxXcc;
-constexpr int CTR_ABORT = kMaxXcc + 1;
-constexpr int CTR_HEADS = kMaxXcc + 2;
-constexpr int CTR_DONE = 2 * kMaxXcc + 2;
-
-__device__ __forceinline__ unsigned xcc_id() {
-    // hardware register 20 (XCC_ID): bits [3:0] are the XCD of the wave
-    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & (kMaxXcc - 1);
-}
-
-__device__ __forceinline__ unsigned ld_relaxed(unsigned* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ bool spin_geq(unsigned* ctr, unsigned target, unsigned* abort_flag) {
-    for (int it = 0; it < SPIN_LIMIT; ++it) {
-        if (ld_relaxed(ctr) >= target) return true;
-        if (ld_relaxed(abort_flag) != 0u) return false;
-        __builtin_amdgcn_s_sleep(2);
-    }
-    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return false;
-}
-
-// Block-wide wait until *ctr >= target (all threads call it); false on abort.
-// Lines of the slot from an earlier generation may still sit in this compute
-// unit's L1: after the counter is reached, an agent-scope acquire invalidates
-// the L1 (the block's waves share it) before the barrier releases the block.
-__device__ __forceinline__ bool block_wait(unsigned* ctr, unsigned target, unsigned* abort_flag, int* sh_ok) {
-    if (threadIdx.x == 0) {
-        const bool ok = spin_geq(ctr, target, abort_flag);
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        *sh_ok = ok ? 1 : 0;
-    }
-    __syncthreads();
-    return *sh_ok != 0;
-}
-
-// Block-wide publish: every wave's loads and stores complete, then one relaxed increment.
-__device__ __forceinline__ void block_signal(unsigned* ctr) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <int N, int M, int PC, int PW, int PR>
-struct FusedCfg {
-    static constexpr int L = M / 2;
-    static constexpr int TC = N / PC;
-    static constexpr int THREADS = PW * TC;
-    static constexpr int TR = L / PR;
-    static constexpr int ROWS = THREADS / TR;
-    static_assert(ROWS * TR == THREADS && ROWS >= 1, "row tile must use the whole block");
-    static constexpr size_t LDS_COL = ((size_t)PW * ColScratch<N, PC>::value + N) * sizeof(float2);
-    static constexpr size_t LDS_ROW = (size_t)ROWS * RowPitch<L, PR>::value * sizeof(float2);
-    static constexpr size_t LDS = LDS_COL > LDS_ROW ? LDS_COL : LDS_ROW;
-};
-
-template <int N, int M, int PC, int PW, int PR, bool REAL, bool FWD>
-__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS), 4) void k_fused(FusedGeom g, FusedBufs bf) {
-    using C = FusedCfg<N, M, PC, PW, PR>;
-    constexpr int L = C::L, ROWS = C::ROWS;
-    extern __shared__ float2 lds[];
-    __shared__ int sh_task, sh_ok, sh_q, sh_nq;
-    unsigned* ctr = bf.ctr;
-    unsigned* abort_flag = ctr + CTR_ABORT;
-    unsigned* heads = ctr + CTR_HEADS;
-    unsigned* done = ctr + CTR_DONE;  // slot s: [2s] column side, [2s+1] row side
-
-    // ---------------- census
-    if (threadIdx.x == 0) {
-        const unsigned x = xcc_id();
-        __hip_atomic_fetch_add(ctr + CTR_CENSUS + x, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(ctr + CTR_ARRIVED, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = spin_geq(ctr + CTR_ARRIVED, gridDim.x, abort_flag) ? 1 : 0;
-        int rank = 0, nq = 0;
-        unsigned mine = 0;
-        for (unsigned y = 0; y < (unsigned)kMaxXcc; ++y) {
-            const unsigned c = ld_relaxed(ctr + CTR_CENSUS + y);
-            if (c != 0u) {
-                rank += (y < x) ? 1 : 0;
-                ++nq;
-            }
-            if (y == x) mine = c;
-        }
-        // the column tasks of a group must leave blocks for its row tasks; the slots exist for Qmax queues
-        if (ok && (mine <= (unsigned)(g.GI * g.npan) || nq > g.Qmax)) {
-            __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            ok = 0;
-        }
-        sh_ok = ok;
-        sh_q = rank;
-        sh_nq = nq;
-    }
-    __syncthreads();
-    if (!sh_ok) return;
-    const int q = sh_q, Q = sh_nq;
-    const int nimg = (q < g.B) ? (g.B - q + Q - 1) / Q : 0;  // images b = q + Q j of this queue
-    const int per_img = g.npan + g.K * g.nrb;
-    const int total = nimg * per_img;
-    const int FG = g.GI * per_img;
-    const size_t plane = (size_t)L * N;
-    const size_t img = (size_t)N * M;
-    float2* qslots = bf.slots + (size_t)q * g.GI * g.S * plane;
-    unsigned* qdone = done + 2 * q * g.GI * g.S;
-
-    for (;;) {
-        __syncthreads();  // the previous task's LDS and shared reads are finished
-        if (threadIdx.x == 0) sh_task = (int)__hip_atomic_fetch_add(&heads[q], 1u, __ATOMIC_RELAXED,
-                                                                     __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int task = sh_task;
-        if (task >= total) return;
-        // an opaque copy of the thread index per task keeps the tiles' address
-        // arithmetic inside the task instead of live across the task loop
-        int tid = (int)threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        const int grp = task / FG, rem = task % FG;
-        const int gi = min(g.GI, nimg - grp * g.GI);
-        if (rem < gi * g.npan) {
-            // ---------------- column task: panel p of image i of the group, all K planes
-            const int i = rem / g.npan, p = rem % g.npan;
-            const int b = q + Q * (grp * g.GI + i);
-            if constexpr (FWD) {
-                float2 xh[PC];
-                col_fwd_setup<N, PC, PW>(bf.A + (size_t)b * plane, p * PW, xh, lds, bf.scale, bf.twN, tid);
-                for (int k = 0; k < g.K; ++k) {
-                    const int s = k % g.S, sl = i * g.S + s;
-                    const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
-                    // the slot's previous plane must have been read by all its row tasks
-                    if (gen > 0 && !block_wait(&qdone[2 * sl + 1], gen * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
-                    col_fwd_emit<N, PC, PW, REAL, false>(xh, bf.filt, k, L, p * PW, qslots + (size_t)sl * plane, lds,
-                                                         bf.twN, tid);
-                    block_signal(&qdone[2 * sl]);
-                }
-            } else {
-                float2 acc[PC];
-#pragma unroll
-                for (int qq = 0; qq < PC; ++qq) acc[qq] = make_float2(0.0f, 0.0f);
-                col_inv_begin<N, PC, PW>(p * PW, lds, tid);
-                for (int k = 0; k < g.K; ++k) {
-                    const int s = k % g.S, sl = i * g.S + s;
-                    const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
-                    // all row tasks of the plane must have written the slot
-                    if (!block_wait(&qdone[2 * sl + 1], (gen + 1) * (unsigned)g.nrb, abort_flag, &sh_ok)) return;
-                    col_inv_accum<N, PC, PW, REAL, false>(qslots + (size_t)sl * plane, bf.filt, k, L, p * PW, acc, lds,
-                                                          bf.twN, tid);
-                    block_signal(&qdone[2 * sl]);
-                }
-                col_inv_finish<N, PC, PW>(acc, p * PW, bf.V + (size_t)b * plane, lds, bf.twN, tid);
-            }
-        } else {
-            // ---------------- row task: tile r of plane (i, k)
-            const int r2 = rem - gi * g.npan;
-            const int k = r2 / (gi * g.nrb);
-            const int i = (r2 / g.nrb) % gi;
-            const int r = r2 % g.nrb;
-            const int b = q + Q * (grp * g.GI + i);
-            const int s = k % g.S, sl = i * g.S + s;
-            const unsigned gen = (unsigned)(grp * ((g.K - s + g.S - 1) / g.S) + k / g.S);
-            if constexpr (FWD) {
-                // all column tasks must have written the plane
-                if (!block_wait(&qdone[2 * sl], (gen + 1) * (unsigned)g.npan, abort_flag, &sh_ok)) return;
-                row_c2r_tile<M, PR, ROWS, false>(qslots + (size_t)sl * plane, bf.cout + ((size_t)b * g.K + k) * img, N,
-                                                 r * ROWS, lds, bf.twL, bf.twM, 1.0f, tid);
-            } else {
-                // the slot's previous plane must have been read by all column tasks
-                if (gen > 0 && !block_wait(&qdone[2 * sl], gen * (unsigned)g.npan, abort_flag, &sh_ok)) return;
-                row_r2c_tile<M, PR, ROWS, false>(bf.cin + ((size_t)b * g.K + k) * img, qslots + (size_t)sl * plane, N,
-                                                 r * ROWS, lds, bf.twL, bf.twM, tid);
-            }
-            block_signal(&qdone[2 * sl + 1]);
-        }
-    }
-}
-
-// ---------------------------------------------------------------- skewed pipeline kernels
-// The batch is cut into chunks of images. Launch i of the forward transform
-// runs the column stage of chunk i+1 and the coefficient row stage of chunk i
-// as one grid (column blocks first), exchanging planes through two ping-pong
-// buffers sized to stay in the on-package cache; kernel boundaries order the
-// stages, so no block waits on another. The inverse runs the coefficient row
-// stage of chunk i+1 with the column stage of chunk i, whose blocks each sum
-// one group of filters into a partial spectrum; one more launch adds the
-// partials in a fixed order and applies the column IFFT.
-
-template <int N, int M, int PC, int PW, int PR, bool REAL>
-__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_fwd(SkewArgs a) {
-    using C = FusedCfg<N, M, PC, PW, PR>;
-    constexpr int L = C::L, ROWS = C::ROWS;
-    extern __shared__ float2 lds[];
-    const size_t plane = (size_t)L * N;
-    const int ncol = a.col_nb * a.npan * a.kg;
-    int task = blockIdx.x;
-    if (task < ncol) {
-        const int g = task % a.kg;
-        const int p = (task / a.kg) % a.npan;
-        const int i = task / (a.kg * a.npan);
-        const int b = a.col_b0 + i;
-        float2 xh[PC];
-        col_fwd_setup<N, PC, PW>(a.A + (size_t)b * plane, p * PW, xh, lds, a.scale, a.twN, (int)threadIdx.x);
-        const int k1 = min(a.K, (g + 1) * a.kper);
-        for (int k = g * a.kper; k < k1; ++k)
-            col_fwd_emit<N, PC, PW, REAL>(xh, a.filt, k, L, p * PW, a.bufC + ((size_t)i * a.K + k) * plane, lds, a.twN, (int)threadIdx.x);
-        return;
-    }
-    task -= ncol;
-    const int r = task % a.nrb;
-    const int k = (task / a.nrb) % a.K;
-    const int i = task / (a.nrb * a.K);
-    const int b = a.row_b0 + i;
-    row_c2r_tile<M, PR, ROWS>(a.bufR + ((size_t)i * a.K + k) * plane, a.cout + ((size_t)b * a.K + k) * N * M, N,
-                              r * ROWS, lds, a.twL, a.twM, 1.0f, (int)threadIdx.x);
-}
-
-template <int N, int M, int PC, int PW, int PR, bool REAL>
-__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_inv(SkewArgs a) {
-    using C = FusedCfg<N, M, PC, PW, PR>;
-    constexpr int L = C::L, ROWS = C::ROWS, TC = C::TC;
-    extern __shared__ float2 lds[];
-    const size_t plane = (size_t)L * N;
-    const int ncol = a.col_nb * a.npan * a.kg;
-    int task = blockIdx.x;
-    if (task < ncol) {
-        const int g = task % a.kg;
-        const int p = (task / a.kg) % a.npan;
-        const int i = task / (a.kg * a.npan);
-        const int b = a.col_b0 + i;
-        float2 acc[PC];
-#pragma unroll
-        for (int q = 0; q < PC; ++q) acc[q] = make_float2(0.0f, 0.0f);
-        col_inv_begin<N, PC, PW>(p * PW, lds, (int)threadIdx.x);
-        const int k1 = min(a.K, (g + 1) * a.kper);
-        for (int k = g * a.kper; k < k1; ++k)
-            col_inv_accum<N, PC, PW, REAL>(a.bufC + ((size_t)i * a.K + k) * plane, a.filt, k, L, p * PW, acc, lds,
-                                           a.twN, (int)threadIdx.x);
-        // partial spectrum of filter group g (and, for packed column 0, its mirrored-term partial)
-        const int t = threadIdx.x % TC, c = threadIdx.x / TC;
-        const int col = p * PW + c;
-        float2* o = a.part + ((size_t)b * a.kg + g) * plane + (size_t)col * N;
-#pragma unroll
-        for (int q = 0; q < PC; ++q) o[t + TC * q] = acc[q];
-        if (col == 0) {
-            // each thread of column 0 reads back the entries of g it accumulated
-            const float2* sg = lds + PW * ColScratch<N, PC>::value;
-            float2* og = a.part0 + ((size_t)b * a.kg + g) * N;
-#pragma unroll
-            for (int q = 0; q < PC; ++q) og[t + TC * q] = sg[t + TC * q];
-        }
-        return;
-    }
-    task -= ncol;
-    const int r = task % a.nrb;
-    const int k = (task / a.nrb) % a.K;
-    const int i = task / (a.nrb * a.K);
-    const int b = a.row_b0 + i;
-    row_r2c_tile<M, PR, ROWS>(a.cin + ((size_t)b * a.K + k) * N * M, a.bufR + ((size_t)i * a.K + k) * plane, N,
-                              r * ROWS, lds, a.twL, a.twM, (int)threadIdx.x);
-}
-
-// V[b] panel p = colIFFT( sum_g partial_g  [+ conj of the mirrored column-0 partials] ), g in order
-template <int N, int M, int PC, int PW, int PR>
-__global__ __launch_bounds__((FusedCfg<N, M, PC, PW, PR>::THREADS)) void k_skew_finish(SkewArgs a) {
-    using C = FusedCfg<N, M, PC, PW, PR>;
-    constexpr int L = C::L, TC = C::TC;
-    extern __shared__ float2 lds[];
-    const size_t plane = (size_t)L * N;
-    const int p = blockIdx.x % a.npan, b = blockIdx.x / a.npan;
-    const int t = threadIdx.x % TC, c = threadIdx.x / TC;
-    const int col = p * PW + c;
-    float2 acc[PC], gg[PC];
-#pragma unroll
-    for (int q = 0; q < PC; ++q) acc[q] = gg[q] = make_float2(0.0f, 0.0f);
-    for (int g = 0; g < a.kg; ++g) {
-        const float2* src = a.part + ((size_t)b * a.kg + g) * plane + (size_t)col * N;
-#pragma unroll
-        for (int q = 0; q < PC; ++q) acc[q] = cadd(acc[q], src[t + TC * q]);
-        if (col == 0) {
-            const float2* sg = a.part0 + ((size_t)b * a.kg + g) * N;
-#pragma unroll
-            for (int q = 0; q < PC; ++q) gg[q] = cadd(gg[q], sg[t + TC * q]);
-        }
-    }
-    if (col == 0) {
-        float2* smir = lds + PW * ColScratch<N, PC>::value;
-#pragma unroll
-        for (int q = 0; q < PC; ++q) smir[t + TC * q] = gg[q];
-    }
-    col_inv_finish<N, PC, PW>(acc, p * PW, a.V + (size_t)b * plane, lds, a.twN, (int)threadIdx.x);
-}
-
 __global__ void k_zero_u32(unsigned* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -1436,158 +1101,6 @@ hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nim
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
                            hipStream_t st) {
     SHEAR_COLS_SWITCH(d.pw_inv, 8, cols_inv_t, d, U, V, nimg, filt, part, st)
-}
-
-// ---------------------------------------------------------------- fused dispatch
-namespace {
-
-// Tile configuration of the fused kernels: 512 threads per block, and the same
-// FFT decompositions as the standalone kernels, so both paths round identically.
-template <int N, int M>
-struct FusedPick {
-    static constexpr int PC = ColPts<N>::value;
-    static constexpr int PW = 512 / (N / PC);
-    static constexpr int PR = Pts<M / 2>::value;
-    using C = FusedCfg<N, M, PC, PW, PR>;
-};
-
-template <int N, int M, bool REAL, bool FWD>
-const void* fused_fn() {
-    using F = FusedPick<N, M>;
-    return reinterpret_cast<const void*>(&k_fused<N, M, F::PC, F::PW, F::PR, REAL, FWD>);
-}
-
-template <int N, int M>
-hipError_t fused_info_t(const DevPlan& d, bool fwd, FusedInfo& fi) {
-    using F = FusedPick<N, M>;
-    using C = typename F::C;
-    fi.threads = C::THREADS;
-    fi.lds = C::LDS;
-    fi.npan = d.L / F::PW;
-    fi.nrb = d.N / C::ROWS;
-    fi.fn = d.real ? (fwd ? fused_fn<N, M, true, true>() : fused_fn<N, M, true, false>())
-                   : (fwd ? fused_fn<N, M, false, true>() : fused_fn<N, M, false, false>());
-    if (C::LDS > 65536) {
-        hipError_t e = hipFuncSetAttribute(fi.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-        if (e != hipSuccess) return e;
-    }
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&fi.blocks_per_cu, fi.fn, C::THREADS, C::LDS);
-}
-
-template <int N>
-hipError_t fused_info_m(const DevPlan& d, bool fwd, FusedInfo& fi) {
-    switch (d.M) {
-        case 128: return fused_info_t<N, 128>(d, fwd, fi);
-        case 256: return fused_info_t<N, 256>(d, fwd, fi);
-        case 512: return fused_info_t<N, 512>(d, fwd, fi);
-        case 1024: return fused_info_t<N, 1024>(d, fwd, fi);
-    }
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
-
-bool fused_supported(int N, int M) {
-    auto ok = [](int n) { return n == 128 || n == 256 || n == 512 || n == 1024; };
-    return ok(N) && ok(M);
-}
-
-hipError_t fused_info(const DevPlan& d, bool fwd, FusedInfo& fi) {
-    switch (d.N) {
-        case 128: return fused_info_m<128>(d, fwd, fi);
-        case 256: return fused_info_m<256>(d, fwd, fi);
-        case 512: return fused_info_m<512>(d, fwd, fi);
-        case 1024: return fused_info_m<1024>(d, fwd, fi);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_fused(const FusedInfo& fi, const FusedGeom& g, const FusedBufs& bf, int grid, hipStream_t st) {
-    FusedGeom ga = g;
-    FusedBufs ba = bf;
-    void* args[] = {&ga, &ba};
-    return hipLaunchCooperativeKernel(fi.fn, dim3((unsigned)grid), dim3((unsigned)fi.threads), args,
-                                      (unsigned)fi.lds, st);
-}
-
-namespace {
-
-template <int N, int M>
-hipError_t skew_t(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st) {
-    using F = FusedPick<N, M>;
-    using C = typename F::C;
-    const void* fn;
-    if (which == 0)
-        fn = d.real ? reinterpret_cast<const void*>(&k_skew_fwd<N, M, F::PC, F::PW, F::PR, true>)
-                    : reinterpret_cast<const void*>(&k_skew_fwd<N, M, F::PC, F::PW, F::PR, false>);
-    else if (which == 1)
-        fn = d.real ? reinterpret_cast<const void*>(&k_skew_inv<N, M, F::PC, F::PW, F::PR, true>)
-                    : reinterpret_cast<const void*>(&k_skew_inv<N, M, F::PC, F::PW, F::PR, false>);
-    else
-        fn = reinterpret_cast<const void*>(&k_skew_finish<N, M, F::PC, F::PW, F::PR>);
-    if (C::LDS > 65536) {
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-        if (e != hipSuccess) return e;
-    }
-    SkewArgs aa = a;
-    void* args[] = {&aa};
-    return hipLaunchKernel(fn, dim3((unsigned)blocks), dim3((unsigned)C::THREADS), args, C::LDS, st);
-}
-
-template <int N>
-hipError_t skew_m(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st) {
-    switch (d.M) {
-        case 128: return skew_t<N, 128>(d, which, a, blocks, st);
-        case 256: return skew_t<N, 256>(d, which, a, blocks, st);
-        case 512: return skew_t<N, 512>(d, which, a, blocks, st);
-        case 1024: return skew_t<N, 1024>(d, which, a, blocks, st);
-    }
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
-
-namespace {
-template <int N, int M>
-SkewTiles tiles_t(const DevPlan& d) {
-    using F = FusedPick<N, M>;
-    SkewTiles t;
-    t.ok = true;
-    t.npan = d.L / F::PW;
-    t.nrb = d.N / F::C::ROWS;
-    return t;
-}
-template <int N>
-SkewTiles tiles_m(const DevPlan& d) {
-    switch (d.M) {
-        case 128: return tiles_t<N, 128>(d);
-        case 256: return tiles_t<N, 256>(d);
-        case 512: return tiles_t<N, 512>(d);
-        case 1024: return tiles_t<N, 1024>(d);
-    }
-    return SkewTiles{};
-}
-}  // namespace
-
-SkewTiles skew_tiles(const DevPlan& d) {
-    switch (d.N) {
-        case 128: return tiles_m<128>(d);
-        case 256: return tiles_m<256>(d);
-        case 512: return tiles_m<512>(d);
-        case 1024: return tiles_m<1024>(d);
-    }
-    return SkewTiles{};
-}
-
-hipError_t launch_skew(const DevPlan& d, int which, const SkewArgs& a, int blocks, hipStream_t st) {
-    if (blocks <= 0) return hipSuccess;
-    switch (d.N) {
-        case 128: return skew_m<128>(d, which, a, blocks, st);
-        case 256: return skew_m<256>(d, which, a, blocks, st);
-        case 512: return skew_m<512>(d, which, a, blocks, st);
-        case 1024: return skew_m<1024>(d, which, a, blocks, st);
-    }
-    return hipErrorInvalidValue;
 }
 
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {

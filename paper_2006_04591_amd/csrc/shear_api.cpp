@@ -46,19 +46,7 @@ struct shear_system {
         hipEvent_t a, b;
     };
     std::vector<Rec> prof;
-    // execution path (shear_set_path)
-    int path = SHEAR_PATH_SEPARATE;
-    int chunk_images = 2;         // pipeline: images per chunk
-    int filters_per_block = 7;    // pipeline: filters per column block
-    shear::SkewTiles tiles;
-    // fused persistent path
-    bool fused = false;           // selected and supported
-    int cus = 0;                  // compute units
-    int fused_slots = 2;          // ring slots per image in flight
-    int fused_group = 0;          // images per group (0: automatic)
-    shear::FusedInfo finfo[2];    // [0] forward, [1] inverse
-    size_t abort_off = 0;         // byte offset of the abort flag in ws (last fused call)
-    bool abort_valid = false;
+    int cus = 0;  // compute units of the device
     // inpainting: the whole iteration sequence of the last call shape, captured as one HIP graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -72,9 +60,6 @@ struct shear_system {
 namespace {
 
 thread_local std::string g_err;
-
-constexpr int kQueues = 8;  // XCDs the fused path sizes its slots and groups for (the kernel counts them)
-constexpr size_t kL2Budget = (size_t)2 << 20;  // exchange slots per XCD
 
 int fail(int code, const std::string& msg) {
     g_err = msg;
@@ -228,18 +213,9 @@ int finish_system(shear_system* s, std::string& why) {
     s->filt_inv = base + b_tw + b_f;
     s->filt_adj = base + b_tw + 2 * b_f;
     s->rms_dev = (const float*)(base + b_tw + 3 * b_f);
-    s->fused = false;
     if ((e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess) {
         why = std::string("querying the compute-unit count failed: ") + hipGetErrorString(e);
         return SHEAR_E_HIP;
-    }
-    if (shear::fused_supported(N, M)) {
-        if ((e = shear::fused_info(s->plan, true, s->finfo[0])) != hipSuccess ||
-            (e = shear::fused_info(s->plan, false, s->finfo[1])) != hipSuccess) {
-            why = std::string("querying the fused kernels failed: ") + hipGetErrorString(e);
-            return SHEAR_E_HIP;
-        }
-        s->tiles = shear::skew_tiles(s->plan);
     }
     return SHEAR_OK;
 }
@@ -279,42 +255,6 @@ int new_system(int rows, int cols, size_t cap, shear_system** out, shear_system*
 }
 
 size_t plane_bytes(const shear_system* s) { return (size_t)s->rows * (s->cols / 2) * sizeof(float2); }
-
-// Geometry of a fused launch for `batch` images; false if the fused path cannot run it.
-bool fused_geom(const shear_system* s, bool fwd, int batch, shear::FusedGeom& g, int& grid) {
-    if (!s->fused) return false;
-    const shear::FusedInfo& fi = s->finfo[fwd ? 0 : 1];
-    if (fi.blocks_per_cu < 1) return false;
-    grid = fi.blocks_per_cu * s->cus;
-    const int per_queue = grid / kQueues;
-    const size_t pb = plane_bytes(s);
-    const int S = std::max(1, std::min(s->fused_slots, s->K));
-    // long column tasks of one group may hold at most half of a queue's blocks,
-    // and a queue's slots should fit in half of its XCD's L2
-    int gi = std::min((per_queue / 2) / fi.npan, (int)(kL2Budget / ((size_t)S * pb)));
-    if (s->fused_group > 0) gi = std::min(s->fused_group, (per_queue - 1) / fi.npan);
-    if (gi < 1) return false;
-    const int nq_max = (batch + kQueues - 1) / kQueues;
-    g.B = batch;
-    g.K = s->K;
-    g.L = s->cols / 2;
-    g.N = s->rows;
-    g.GI = std::min(gi, nq_max);
-    g.S = S;
-    g.Qmax = kQueues;
-    g.npan = fi.npan;
-    g.nrb = fi.nrb;
-    return true;
-}
-
-size_t fused_slot_planes(const shear::FusedGeom& g) { return (size_t)g.Qmax * g.GI * g.S; }
-
-// Workspace layout of a fused call: [batch planes A or V][ring slots][counters].
-size_t fused_ws_needed(const shear_system* s, const shear::FusedGeom& g) {
-    const size_t pb = plane_bytes(s);
-    return (size_t)g.B * pb + fused_slot_planes(g) * pb +
-           ((shear::fused_ctr_words(g) * sizeof(unsigned) + 255) & ~(size_t)255);
-}
 
 // Separate-path workspace: [batch planes A or V][chunk x K exchange planes][inverse partial sums of chunk images].
 size_t part_bytes(const shear_system* s, int chunk) { return shear::cols_inv_part_elems(s->plan, chunk) * sizeof(float2); }
@@ -383,15 +323,6 @@ int prepare_ws(shear_system* s, int batch, int& chunk) {
     return ensure_ws(s, ws_needed(s, batch, chunk));
 }
 
-// Fused path workspace; returns false (no error) when it does not fit the cap.
-bool prepare_fused_ws(shear_system* s, const shear::FusedGeom& g, int& rc) {
-    rc = SHEAR_OK;
-    const size_t need = fused_ws_needed(s, g);
-    if (need > s->ws_cap) return false;
-    rc = ensure_ws(s, need);
-    return rc == SHEAR_OK;
-}
-
 hipError_t take_event(shear_system* s, hipEvent_t& e) {
     if (!s->ev_free.empty()) {
         e = s->ev_free.back();
@@ -416,162 +347,10 @@ hipError_t timed(shear_system* s, int kind, hipStream_t st, F&& launch) {
     return hipSuccess;
 }
 
-// ---------------------------------------------------------------- pipeline path helpers
-
-struct PipeGeom {
-    int chunk, nchunks, kper, kg;
-    size_t xbuf;  // bytes of one exchange buffer
-};
-
-PipeGeom pipe_geom(const shear_system* s, int batch) {
-    PipeGeom g;
-    g.chunk = std::max(1, std::min(s->chunk_images, batch));
-    g.nchunks = (batch + g.chunk - 1) / g.chunk;
-    g.kper = std::max(1, std::min(s->filters_per_block, s->K));
-    g.kg = (s->K + g.kper - 1) / g.kper;
-    g.xbuf = (size_t)g.chunk * s->K * plane_bytes(s);
-    return g;
-}
-
-// forward: [A: batch planes][2 exchange buffers]
-// inverse: [V: batch planes][2 exchange buffers][partials: batch*kg planes][partial columns: batch*kg*N]
-size_t pipe_ws_needed(const shear_system* s, int batch, bool fwd) {
-    const PipeGeom g = pipe_geom(s, batch);
-    const size_t pb = plane_bytes(s);
-    size_t need = (size_t)batch * pb + 2 * g.xbuf;
-    if (!fwd) need += (size_t)batch * g.kg * pb + (size_t)batch * g.kg * s->rows * sizeof(float2);
-    return need;
-}
-
-bool pipe_usable(const shear_system* s) { return s->path == SHEAR_PATH_PIPELINE && s->tiles.ok; }
-
-shear::SkewArgs pipe_args(const shear_system* s, const PipeGeom& g) {
-    shear::SkewArgs a{};
-    a.K = s->K;
-    a.L = s->cols / 2;
-    a.N = s->rows;
-    a.npan = s->tiles.npan;
-    a.nrb = s->tiles.nrb;
-    a.kper = g.kper;
-    a.kg = g.kg;
-    a.twN = s->plan.twN;
-    a.twL = s->plan.twL;
-    a.twM = s->plan.twM;
-    return a;
-}
-
-int forward_pipeline(shear_system* s, const float* x, float* coeffs, int batch, hipStream_t st) {
-    const PipeGeom g = pipe_geom(s, batch);
-    int rc = ensure_ws(s, pipe_ws_needed(s, batch, true));
-    if (rc != SHEAR_OK) return rc;
-    const shear::DevPlan& d = s->plan;
-    const size_t pb = plane_bytes(s);
-    char* base = (char*)s->ws;
-    float2* A = (float2*)base;
-    float2* X[2] = {(float2*)(base + (size_t)batch * pb), (float2*)(base + (size_t)batch * pb + g.xbuf)};
-    hipError_t e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st,
-                         [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
-    if (e != hipSuccess) return hip_fail(e, "row r2c launch");
-    shear::SkewArgs a = pipe_args(s, g);
-    a.A = A;
-    a.cout = coeffs;
-    a.filt = s->filt_fwd;
-    a.scale = (float)(1.0 / ((double)d.N * d.M));  // 1/(N M): a power of two, exact
-    for (int i = -1; i < g.nchunks; ++i) {
-        const int ci = i + 1;  // chunk of the column stage
-        a.col_b0 = ci * g.chunk;
-        a.col_nb = ci < g.nchunks ? std::min(g.chunk, batch - a.col_b0) : 0;
-        a.bufC = X[ci & 1];
-        a.row_b0 = i * g.chunk;
-        a.row_nb = i >= 0 ? std::min(g.chunk, batch - a.row_b0) : 0;
-        a.bufR = X[(i + 2) & 1];
-        const int blocks = a.col_nb * a.npan * a.kg + a.row_nb * a.K * a.nrb;
-        e = timed(s, SHEAR_KERNEL_PIPE_FWD, st, [&] { return shear::launch_skew(d, 0, a, blocks, st); });
-        if (e != hipSuccess) return hip_fail(e, "pipeline forward launch");
-    }
-    return SHEAR_OK;
-}
-
-int inverse_pipeline(shear_system* s, const float* coeffs, float* x, int batch, hipStream_t st, const void* filt) {
-    const PipeGeom g = pipe_geom(s, batch);
-    int rc = ensure_ws(s, pipe_ws_needed(s, batch, false));
-    if (rc != SHEAR_OK) return rc;
-    const shear::DevPlan& d = s->plan;
-    const size_t pb = plane_bytes(s);
-    char* base = (char*)s->ws;
-    float2* V = (float2*)base;
-    char* p = base + (size_t)batch * pb;
-    float2* U[2] = {(float2*)p, (float2*)(p + g.xbuf)};
-    p += 2 * g.xbuf;
-    float2* part = (float2*)p;
-    p += (size_t)batch * g.kg * pb;
-    float2* part0 = (float2*)p;
-    shear::SkewArgs a = pipe_args(s, g);
-    a.cin = coeffs;
-    a.part = part;
-    a.part0 = part0;
-    a.V = V;
-    a.filt = filt;
-    hipError_t e;
-    for (int i = -1; i < g.nchunks; ++i) {
-        const int ri = i + 1;  // chunk of the row stage
-        a.row_b0 = ri * g.chunk;
-        a.row_nb = ri < g.nchunks ? std::min(g.chunk, batch - a.row_b0) : 0;
-        a.bufR = U[ri & 1];
-        a.col_b0 = i * g.chunk;
-        a.col_nb = i >= 0 ? std::min(g.chunk, batch - a.col_b0) : 0;
-        a.bufC = U[(i + 2) & 1];
-        const int blocks = a.col_nb * a.npan * a.kg + a.row_nb * a.K * a.nrb;
-        e = timed(s, SHEAR_KERNEL_PIPE_INV, st, [&] { return shear::launch_skew(d, 1, a, blocks, st); });
-        if (e != hipSuccess) return hip_fail(e, "pipeline inverse launch");
-    }
-    e = timed(s, SHEAR_KERNEL_PIPE_FINISH, st, [&] { return shear::launch_skew(d, 2, a, batch * a.npan, st); });
-    if (e != hipSuccess) return hip_fail(e, "pipeline finish launch");
-    e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st, [&] { return shear::launch_rows_c2r(d, V, x, batch, 1.0f, false, st); });
-    if (e != hipSuccess) return hip_fail(e, "row c2r launch");
-    return SHEAR_OK;
-}
-
 int inverse_like(shear_system* s, const float* coeffs, float* x, int batch, void* stream, const void* filt) {
     int rc = check_call(s, coeffs, x, batch, true);
     if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
-    if (pipe_usable(s)) {
-        s->abort_valid = false;
-        if (pipe_ws_needed(s, batch, false) <= s->ws_cap) return inverse_pipeline(s, coeffs, x, batch, (hipStream_t)stream, filt);
-    }
-    shear::FusedGeom g{};
-    int grid = 0;
-    if (fused_geom(s, false, batch, g, grid)) {
-        if (prepare_fused_ws(s, g, rc)) {
-            const shear::DevPlan& d = s->plan;
-            hipStream_t st = (hipStream_t)stream;
-            const size_t pb = plane_bytes(s);
-            char* base = (char*)s->ws;
-            shear::FusedBufs bf{};
-            bf.V = (float2*)base;
-            bf.slots = (float2*)(base + (size_t)batch * pb);
-            bf.ctr = (unsigned*)(base + (size_t)batch * pb + fused_slot_planes(g) * pb);
-            bf.cin = coeffs;
-            bf.filt = filt;
-            bf.twN = d.twN;
-            bf.twL = d.twL;
-            bf.twM = d.twM;
-            const int nw = (int)shear::fused_ctr_words(g);
-            hipError_t e = shear::launch_zero_u32(bf.ctr, nw, st);
-            if (e != hipSuccess) return hip_fail(e, "counter reset launch");
-            e = timed(s, SHEAR_KERNEL_FUSED_INV, st, [&] { return shear::launch_fused(s->finfo[1], g, bf, grid, st); });
-            if (e != hipSuccess) return hip_fail(e, "fused inverse launch");
-            s->abort_off = (size_t)((char*)(bf.ctr + shear::fused_abort_word()) - base);
-            s->abort_valid = true;
-            e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
-                      [&] { return shear::launch_rows_c2r(d, bf.V, x, batch, 1.0f, false, st); });
-            if (e != hipSuccess) return hip_fail(e, "row c2r launch");
-            return SHEAR_OK;
-        }
-        if (rc != SHEAR_OK) return rc;
-    }
-    s->abort_valid = false;
     int chunk = 0;
     if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
     const shear::DevPlan& d = s->plan;
@@ -758,19 +537,9 @@ int shear_workspace_bytes(const shear_system* s, int batch, size_t* bytes) {
     if (!s || !bytes) return fail(SHEAR_E_INVALID, "NULL argument");
     if (batch <= 0) return fail(SHEAR_E_INVALID, "batch must be positive");
     size_t need = 0;
-    for (int fwd = 0; fwd < 2; ++fwd) {
-        shear::FusedGeom g{};
-        int grid = 0;
-        if (pipe_usable(s) && pipe_ws_needed(s, batch, fwd != 0) <= s->ws_cap) {
-            need = std::max(need, pipe_ws_needed(s, batch, fwd != 0));
-        } else if (fused_geom(s, fwd != 0, batch, g, grid) && fused_ws_needed(s, g) <= s->ws_cap) {
-            need = std::max(need, fused_ws_needed(s, g));
-        } else {
-            const int chunk = chunk_images(s, batch);
-            if (chunk < 1) return fail(SHEAR_E_NOMEM, "workspace cap too small for one image");
-            need = std::max(need, ws_needed(s, batch, chunk));
-        }
-    }
+    const int chunk = chunk_images(s, batch);
+    if (chunk < 1) return fail(SHEAR_E_NOMEM, "workspace cap too small for one image");
+    need = ws_needed(s, batch, chunk);
     *bytes = need;
     return SHEAR_OK;
 }
@@ -782,84 +551,10 @@ int shear_reserve(shear_system* s, int batch) {
     return ensure_ws(s, need);
 }
 
-int shear_set_path(shear_system* s, int path, int chunk_images, int filters_per_block) {
-    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
-    if (path != SHEAR_PATH_PIPELINE && path != SHEAR_PATH_SEPARATE && path != SHEAR_PATH_PERSISTENT)
-        return fail(SHEAR_E_INVALID, "unknown path " + std::to_string(path));
-    if (path != SHEAR_PATH_SEPARATE && !shear::fused_supported(s->rows, s->cols))
-        return fail(SHEAR_E_SIZE, "this path needs rows and cols in {128, 256, 512, 1024}");
-    if (path == SHEAR_PATH_PERSISTENT) {
-        const bool ok = s->cus >= kQueues && s->finfo[0].blocks_per_cu > 0 && s->finfo[1].blocks_per_cu > 0;
-        if (!ok) return fail(SHEAR_E_HIP, "the persistent kernels cannot be resident on this device");
-    }
-    if (path == SHEAR_PATH_PIPELINE && !s->tiles.ok) return fail(SHEAR_E_SIZE, "no pipeline tiles for this size");
-    s->path = path;
-    s->fused = path == SHEAR_PATH_PERSISTENT;
-    if (path == SHEAR_PATH_PERSISTENT) {
-        if (chunk_images > 0) s->fused_group = chunk_images;
-        if (filters_per_block > 0) s->fused_slots = filters_per_block;
-    } else {
-        if (chunk_images > 0) s->chunk_images = chunk_images;
-        if (filters_per_block > 0) s->filters_per_block = filters_per_block;
-    }
-    return SHEAR_OK;
-}
-
-int shear_check(shear_system* s, void* hip_stream) {
-    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
-    hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-    if (!s->abort_valid || !s->ws) return SHEAR_OK;
-    unsigned flag = 0;
-    e = hipMemcpy(&flag, (char*)s->ws + s->abort_off, sizeof(flag), hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "reading the fused-kernel status");
-    if (flag != 0u)
-        return fail(SHEAR_E_HIP, "a fused kernel gave up waiting on a dependency (bounded spin expired); its output is invalid");
-    return SHEAR_OK;
-}
-
 int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, void* stream) {
     int rc = check_call(s, x, coeffs, batch, true);
     if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
-    if (pipe_usable(s)) {
-        s->abort_valid = false;
-        if (pipe_ws_needed(s, batch, true) <= s->ws_cap) return forward_pipeline(s, x, coeffs, batch, (hipStream_t)stream);
-    }
-    shear::FusedGeom g{};
-    int grid = 0;
-    if (fused_geom(s, true, batch, g, grid)) {
-        if (prepare_fused_ws(s, g, rc)) {
-            const shear::DevPlan& d = s->plan;
-            hipStream_t st = (hipStream_t)stream;
-            const size_t pb = plane_bytes(s);
-            char* base = (char*)s->ws;
-            shear::FusedBufs bf{};
-            float2* A = (float2*)base;
-            bf.A = A;
-            bf.slots = (float2*)(base + (size_t)batch * pb);
-            bf.ctr = (unsigned*)(base + (size_t)batch * pb + fused_slot_planes(g) * pb);
-            bf.cout = coeffs;
-            bf.filt = s->filt_fwd;
-            bf.twN = d.twN;
-            bf.twL = d.twL;
-            bf.twM = d.twM;
-            bf.scale = (float)(1.0 / ((double)d.N * d.M));  // 1/(N M): a power of two, exact
-            hipError_t e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st,
-                                 [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
-            if (e != hipSuccess) return hip_fail(e, "row r2c launch");
-            const int nw = (int)shear::fused_ctr_words(g);
-            e = shear::launch_zero_u32(bf.ctr, nw, st);
-            if (e != hipSuccess) return hip_fail(e, "counter reset launch");
-            e = timed(s, SHEAR_KERNEL_FUSED_FWD, st, [&] { return shear::launch_fused(s->finfo[0], g, bf, grid, st); });
-            if (e != hipSuccess) return hip_fail(e, "fused forward launch");
-            s->abort_off = (size_t)((char*)(bf.ctr + shear::fused_abort_word()) - base);
-            s->abort_valid = true;
-            return SHEAR_OK;
-        }
-        if (rc != SHEAR_OK) return rc;
-    }
-    s->abort_valid = false;
     int chunk = 0;
     if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
     const shear::DevPlan& d = s->plan;
@@ -901,7 +596,6 @@ int shear_denoise(shear_system* s, const float* x, float* y, int batch, const fl
     if (!thresholds) return fail(SHEAR_E_INVALID, "thresholds pointer is NULL");
     int chunk = 0;
     if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
-    s->abort_valid = false;
     const shear::DevPlan& d = s->plan;
     hipStream_t st = (hipStream_t)stream;
     const size_t pb = plane_bytes(s) / sizeof(float2);
@@ -996,7 +690,6 @@ int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, flo
     if (iterations < 1) return fail(SHEAR_E_INVALID, "iterations must be positive");
     int chunk = 0;
     if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
-    s->abort_valid = false;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e;
     if (s->prof_on) {

@@ -196,7 +196,6 @@ def test_profile_counts(cfg1, gpu):
     s, _, x = cfg1
     _say("case: per-launch timing")
     xg = _to(x[None], gpu)
-    s.set_path("separate")
     s.profile(True)
     c = s.forward(xg)
     s.inverse(c)
@@ -349,82 +348,6 @@ def test_config4_256_k33_b32_sampled(gpu, lib):
                 want = _plane_forward(x64, ref.spectra[k])
                 assert np.linalg.norm(c[b, k].double().cpu().numpy() - want) <= TOL * np.linalg.norm(x64) * ref.rms[k]
             assert _rel(a[b].cpu().numpy(), OT.adjoint_plain(g[b].astype(np.float64), ref.spectra)) <= TOL
-
-
-# ---------------------------------------------------------------- execution paths
-
-
-@pytest.mark.parametrize("N,M,J,B", [(128, 128, 2, 1), (256, 256, 3, 3), (256, 512, 3, 9), (512, 512, 4, 16),
-                                     (1024, 1024, 4, 2), (512, 128, 2, 5)])
-def test_paths_agree(gpu, lib, N, M, J, B):
-    """separate (default), pipeline and persistent paths: the forward transform is bitwise identical
-    (same per-element operations in the same order). The inverse sums the filters in the same order
-    on every path except the pipeline (filter-group partial sums), but the compiler may contract
-    multiply-adds differently in different kernels, so the inverses agree to rounding."""
-    from paper_2006_04591_amd import ShearletSystem
-
-    _say(f"case: paths {N}x{M} J={J} B={B}")
-    with ShearletSystem.build(N, M, J) as s:
-        x = _to(synth.cartoon_batch(B, N, M, config=7, sigma=10.0), gpu)
-        out = {}
-        for path in ("separate", "pipeline", "persistent"):
-            s.set_path(path)
-            c = s.forward(x)
-            y = s.inverse(c)
-            a = s.adjoint(c)
-            s.check()
-            out[path] = (c, y, a)
-        torch.cuda.synchronize()
-        c0, y0, a0 = out["separate"]
-        for path in ("pipeline", "persistent"):
-            c1, y1, a1 = out[path]
-            assert torch.equal(c0, c1), path
-        for path in ("pipeline", "persistent"):
-            ey = _rel(out[path][1].cpu().numpy(), y0.cpu().numpy())
-            ea = _rel(out[path][2].cpu().numpy(), a0.cpu().numpy())
-            my = float((out[path][1] - y0).abs().max() / y0.abs().max())
-            print(f"{path}: inverse vs separate {ey:.2e} (max {my:.2e}), adjoint vs separate {ea:.2e}")
-            assert ey <= 1e-6 and ea <= 1e-6, path
-            assert _rel(out[path][1].cpu().numpy(), x.cpu().numpy()) <= TOL
-
-
-@pytest.mark.parametrize("chunk,fpb", [(1, 49), (3, 5), (16, 1), (5, 8)])
-def test_pipeline_chunking(cfg2, gpu, chunk, fpb):
-    s, ref = cfg2
-    _say(f"case: pipeline chunk={chunk} filters/block={fpb} 512x512 B=7")
-    x = synth.cartoon_batch(7, 512, 512, config=2, sigma=30.0)
-    xg = _to(x, gpu)
-    s.set_path("pipeline", chunk, fpb)
-    c = s.forward(xg)
-    y = s.inverse(c)
-    s.set_path("separate")
-    c0 = s.forward(xg)
-    s.set_path("separate")
-    torch.cuda.synchronize()
-    assert torch.equal(c, c0)
-    assert _rel(y.cpu().numpy(), x) <= TOL
-    x64 = x[3].astype(np.float64)
-    for k in (0, 30, 48):
-        want = _plane_forward(x64, ref.spectra[k])
-        assert np.linalg.norm(c[3, k].double().cpu().numpy() - want) <= TOL * np.linalg.norm(x64) * ref.rms[k]
-
-
-def test_path_profile_kinds(cfg1, gpu):
-    s, _, x = cfg1
-    _say("case: per-path launch timing kinds")
-    xg = _to(x[None], gpu)
-    rec = {}
-    for path in ("pipeline", "persistent"):
-        s.set_path(path)
-        s.profile(True)
-        s.inverse(s.forward(xg))
-        rec[path] = s.profile_read()
-        s.profile(False)
-        s.check()
-    s.set_path("separate")
-    assert rec["persistent"]["fused_fwd"][0] == 1 and rec["persistent"]["fused_inv"][0] == 1
-    assert rec["pipeline"]["pipe_fwd"][0] == 2 and rec["pipeline"]["pipe_inv"][0] == 2
-    assert rec["pipeline"]["pipe_finish"][0] == 1 and rec["pipeline"]["cols_fwd"][0] == 0
 
 
 # ---------------------------------------------------------------- column-pass schedules and the autotuner
