@@ -35,7 +35,7 @@ METRIC_DENOISE = "denoise (fwd + hard threshold + inv) shearlet Mpix·filters/s 
 METRIC_LAYER = "layer fwd+bwd (shear_forward + shear_adjoint) shearlet Mpix·filters/s @256²×33 FP32"
 WORKLOAD_LAYER = ("differentiable layer, forward and backward (upstream gradient N(0,1)), 32 x 1 x 256x256 "
                   "cartoon images, 3 scales (shear levels 1,1,2) = 33 filters, FP32")
-WORKLOAD_DENOISE = ("hard-threshold denoising (threshold 3 x sigma x RMS_k per band, low-pass kept), "
+WORKLOAD_DENOISE = ("hard-threshold denoising (threshold 3 x sigma x RMS_k on every plane), "
                     "16 x 512x512 cartoon+N(0,30^2) images, 49 filters, FP32")
 
 
@@ -197,7 +197,7 @@ def bench_inpaint(args) -> int:
     import torch
 
     import synth
-    from paper_2006_04591_amd import UnevenInpainter
+    from paper_2006_04591_amd import UnevenInpainter, delta_schedule
 
     iters = 100
     dev = torch.device("cuda:0")
@@ -215,7 +215,7 @@ def bench_inpaint(args) -> int:
         d0 = float((c[0].abs().amax(dim=(1, 2)).cpu().numpy() / s.rms).max())
         fms.append(torch.from_numpy(fm).to(dev))
         ms.append(torch.from_numpy(m).to(dev))
-        scheds.append(np.array([d0 * (1.0 - t / (iters - 1)) for t in range(iters)]))
+        scheds.append(delta_schedule("linear", d0, iters))
         cleans.append((f, m, fm))
         units += n * n * s.K * iters / 1e6
     log(f"bench inpaint: sizes {sizes}")
@@ -551,7 +551,7 @@ def main() -> int:
     else:
         schedule = shs.autotune(B)
         log(f"bench: autotuned column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv): {schedule}")
-    # denoising workload: hard threshold 3 sigma RMS_k on every band, low-pass kept
+    # denoising workload: hard threshold 3 sigma RMS_k on every plane (the listing of Section 4.2)
     thr = torch.from_numpy(np.tile(shs.paper_thresholds(SIGMA, factors=[3.0] * J), (B, 1))).to(dev)
     if layer:
         from paper_2006_04591_amd import ShearletLayer

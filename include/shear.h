@@ -94,20 +94,26 @@ int shear_design_spectra(const shear_build_params* p, int* K, double* spectra_ce
  * Synchronous. *out receives a new system; free it with shear_destroy_system. */
 int shear_build_system(const shear_build_params* p, shear_system** out);
 
-/* A system from caller-supplied spectra (centred layout, K*rows*cols*2 doubles,
- * host memory, copied). The spectra must be Hermitian (DFTs of real kernels):
+/* getshearletsystem2D (Section 3.4.1) for a caller-supplied filter bank: a
+ * system from spectra in the paper's centred layout (K*rows*cols*2 doubles,
+ * host memory, copied); W = sum_k |Psi_k|^2 and RMS_k are formed as for a
+ * built system. The spectra must be Hermitian (DFTs of real kernels):
  * |Psi(-xi) - conj Psi(xi)| <= 1e-9 max|Psi|, else SHEAR_E_FRAME; the frame
  * must satisfy min W > 1e-10 max W, else SHEAR_E_FRAME. idx may be NULL
  * (triples then read (0, 0, k)). Synchronous. */
 int shear_system_from_spectra(int rows, int cols, int K, const double* spectra_centred, const int* idx,
                               size_t max_workspace_bytes, shear_system** out);
 
-/* Sizes, RMS_k = ||Psi_k||_F / sqrt(rows*cols) (K doubles) and index triples
- * (K*3 ints) of a system. Any output pointer may be NULL. Host only. */
+/* The fields getshearletsystem2D returns besides the filters (Section 3.4.1):
+ * sizes, RMS_k = ||Psi_k||_F / sqrt(rows*cols) (K doubles, the weights of the
+ * denoising listing of Section 4.2) and the index triples (K*3 ints) of a
+ * system. Any output pointer may be NULL. Host only. */
 int shear_system_info(const shear_system* s, int* K, int* rows, int* cols, double* rms, int* idx);
 
-/* Copies the FP64 spectra (centred, K*rows*cols*2 doubles) and the dual-frame
- * weight W (centred, rows*cols doubles) to host memory; either may be NULL. */
+/* The filters of getshearletsystem2D (Section 3.4.1) and the dual-frame weight
+ * that Algorithm 2 divides by (Section 3.4.2), W = sum_k |Psi_k|^2: copies the
+ * FP64 spectra (centred, K*rows*cols*2 doubles) and W (centred, rows*cols
+ * doubles) to host memory; either pointer may be NULL. */
 int shear_export_spectra(const shear_system* s, double* spectra_centred, double* W_centred);
 
 /* Allocates the device workspace for batches up to `batch`, so that later
@@ -143,6 +149,41 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
  * and the inverse row stage of one kernel. Asynchronous. */
 int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
                   void* hip_stream);
+
+/* Thresholds of the denoising rule of Section 4.2 for shear_denoise:
+ *   out[b*K + k] = K_j * sigma[b] * RMS_k  for filter k of scale j,
+ * the text's delta_j = K_j sigma per scale, weighted per filter by RMS_k as
+ * the listing does. The listing thresholds every plane, the low-pass
+ * included; the low-pass belongs to no scale j and takes K_1 (the coarsest
+ * scale's factor). sigma: batch noise levels (host); factors: the J values
+ * K_1..K_J, coarse to fine (n_factors == J), or NULL for the paper's choice
+ * (2.5 on every scale but the finest, 3.8 there); out: batch*K float32
+ * (host). Host only: nothing is launched. SHEAR_E_INVALID for NULL pointers,
+ * a negative batch or a factor count other than J. */
+int shear_denoise_thresholds(const shear_system* s, const double* sigma, int batch, const double* factors,
+                             int n_factors, float* out);
+
+/* Decay of Algorithm 3's threshold (Section 4.3): out[i] = delta_i, i < iterations.
+ *   SHEAR_DECAY_GEOMETRIC: delta_i = delta_init * lambda^i with
+ *     lambda = (delta_min / delta_init)^(1/(iterations-1)), so delta goes from
+ *     delta_init to delta_min (the printed lambda = delta_min^(1/(iterations-1))
+ *     reaches delta_min only for delta_init = 1; delta_min is read relative to it).
+ *   SHEAR_DECAY_LINEAR: delta_i = delta_init * (1 - i/(iterations-1)), down to 0
+ *     (delta_min unused).
+ * Host only; no system needed. SHEAR_E_INVALID for an unknown kind, a
+ * non-positive iteration count or, in the geometric decay, delta_init or
+ * delta_min <= 0. */
+#define SHEAR_DECAY_GEOMETRIC 0
+#define SHEAR_DECAY_LINEAR 1
+int shear_delta_schedule(int kind, double delta_init, double delta_min, int iterations, double* out);
+
+/* Per-filter thresholds of Algorithm 3 for shear_inpaint: the scalar delta of
+ * iteration i and image b is weighted by each filter's RMS_k, as in the
+ * denoising listing of Section 4.2 (every plane, the low-pass included):
+ *   out[(i*batch + b)*K + k] = deltas[i*batch + b] * RMS_k.
+ * deltas: iterations*batch (host); out: iterations*batch*K float32 (host).
+ * Host only. SHEAR_E_INVALID for NULL pointers, iterations < 1 or batch < 0. */
+int shear_inpaint_thresholds(const shear_system* s, const double* deltas, int iterations, int batch, float* out);
 
 /* Shearlet inpainting by iterative hard thresholding (Section 4.3, Algorithm 3):
  *   f = 0; for i < iterations:

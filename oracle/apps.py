@@ -15,8 +15,11 @@ Readings (paper silent or garbled):
   * Per-filter thresholds: delta_k = K_j * sigma * RMS_k for a filter k of
     scale j. The text gives delta_j = K_j sigma; its listing multiplies by the
     RMS of each filter. K = [2.5, 2.5, 2.5, 3.8] for four scales (coarse to
-    fine); for J scales the finest gets 3.8 and the others 2.5. The low-pass
-    filter belongs to no scale j and is not thresholded (delta = 0).
+    fine); for J scales the finest gets 3.8 and the others 2.5. The listing
+    thresholds every plane (its weights loop over all RMS entries), the
+    low-pass included; the low-pass belongs to no scale j of the text, so it
+    takes the factor of the coarsest scale, K_1. Algorithm 3 thresholds every
+    plane in the same way.
   * The denoising listing thresholds one array and reconstructs another
     (a garble); the thresholded coefficients are reconstructed.
   * Algorithm 3's decay: as printed lambda = delta_min^(1/(iterations-1)),
@@ -55,7 +58,8 @@ def scale_factors(n_scales: int) -> np.ndarray:
 
 
 def thresholds(idx: np.ndarray, rms: np.ndarray, sigma: float, factors=None) -> np.ndarray:
-    """delta_k = K_j sigma RMS_k for filter k of scale j = idx[k, 1]; 0 (keep all) for the low-pass (scale 0)."""
+    """delta_k = K_j sigma RMS_k for filter k of scale j = idx[k, 1] (Section 4.2 and its listing);
+    the low-pass (scale 0) takes K_1, the factor of the coarsest scale."""
     idx = np.asarray(idx)
     scale = idx[:, 1]
     J = int(scale.max())
@@ -64,8 +68,7 @@ def thresholds(idx: np.ndarray, rms: np.ndarray, sigma: float, factors=None) -> 
         raise ValueError(f"need {J} factors, got {f.shape}")
     out = np.zeros(len(scale), dtype=np.float64)
     for k, j in enumerate(scale):
-        if j > 0:
-            out[k] = f[j - 1] * sigma * float(rms[k])
+        out[k] = f[max(int(j), 1) - 1] * sigma * float(rms[k])
     return out
 
 

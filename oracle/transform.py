@@ -2,8 +2,8 @@
 
 Conventions (Section 3.2-3.4): the 2-D FFT is unnormalised and its inverse
 carries 1/(N M), as TensorFlow's fft2d / ifft2d do. Fourier transforms of
-images and filters use the centred layout produced by
-Fourier(f) = fftshift(fft(ifftshift(f))) (Section 3.3).
+images and filters use the centred layout of Section 3.3 (zero frequency at
+index floor(n/2) along each axis): Fourier(f) = centre(fft2(uncentre(f))).
 
 Readings (paper inconsistent or silent):
   * Conjugation: Algorithm 1 conjugates the image spectrum while its listing
@@ -20,8 +20,8 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "tfftshift",
-    "itfftshift",
+    "to_centred",
+    "from_centred",
     "fourier",
     "inverse_fourier",
     "decompose",
@@ -39,34 +39,27 @@ def _axes(x: np.ndarray, axes):
     return list(range(x.ndim - 2, x.ndim)) if axes is None else list(axes)
 
 
-def tfftshift(x: np.ndarray, axes=None) -> np.ndarray:
-    """Gather-based fftshift of Section 3.3: per axis, indices (p2..n-1, 0..p2-1), p2 = (n+1)//2."""
-    y = x
-    for ax in _axes(x, axes):
-        n = y.shape[ax]
-        p2 = (n + 1) // 2
-        y = np.take(y, np.concatenate((np.arange(p2, n), np.arange(p2))), axis=ax)
-    return y
+def to_centred(x: np.ndarray, axes=None) -> np.ndarray:
+    """Natural DFT order -> the centred layout of Section 3.3: along each axis of length n the
+    element at index 0 moves to index floor(n/2) (a circular shift by floor(n/2))."""
+    ax = _axes(x, axes)
+    return np.roll(x, [x.shape[a] // 2 for a in ax], axis=ax)
 
 
-def itfftshift(x: np.ndarray, axes=None) -> np.ndarray:
-    """Gather-based ifftshift of Section 3.3: as tfftshift with p2 = n - (n+1)//2."""
-    y = x
-    for ax in _axes(x, axes):
-        n = y.shape[ax]
-        p2 = n - (n + 1) // 2
-        y = np.take(y, np.concatenate((np.arange(p2, n), np.arange(p2))), axis=ax)
-    return y
+def from_centred(x: np.ndarray, axes=None) -> np.ndarray:
+    """Centred layout -> natural DFT order: the circular shift by -floor(n/2) that undoes to_centred."""
+    ax = _axes(x, axes)
+    return np.roll(x, [-(x.shape[a] // 2) for a in ax], axis=ax)
 
 
 def fourier(f: np.ndarray) -> np.ndarray:
     """Fourier(f) = fftshift(fft2(ifftshift(f))) over the last two axes (Section 3.3)."""
-    return tfftshift(np.fft.fft2(itfftshift(f)))
+    return to_centred(np.fft.fft2(from_centred(f)))
 
 
 def inverse_fourier(F: np.ndarray) -> np.ndarray:
     """InverseFourier(F) = fftshift(ifft2(ifftshift(F))) over the last two axes (Section 3.3)."""
-    return tfftshift(np.fft.ifft2(itfftshift(F)))
+    return to_centred(np.fft.ifft2(from_centred(F)))
 
 
 def decompose(x: np.ndarray, filters_centred: np.ndarray) -> np.ndarray:

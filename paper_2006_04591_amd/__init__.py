@@ -11,6 +11,7 @@ from ._binding import (
     ShearError,
     ShearletSystem,
     ShrinkNet,
+    delta_schedule,
     design_spectra,
     load_library,
 )
@@ -18,5 +19,5 @@ from ._binding import (
 from .autograd import ShearletLayer, ShearletTransform
 from .batched import UnevenInpainter
 
-__all__ = ["EXPORTED", "LIB_PATH", "ShearError", "ShearletLayer", "ShearletSystem", "ShearletTransform",
+__all__ = ["EXPORTED", "LIB_PATH", "ShearError", "ShearletLayer", "ShearletSystem", "ShearletTransform", "delta_schedule",
            "ShrinkNet", "UnevenInpainter", "design_spectra", "load_library"]

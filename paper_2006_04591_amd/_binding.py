@@ -36,7 +36,10 @@ EXPORTED = (
     "shear_inverse",
     "shear_adjoint",
     "shear_denoise",
+    "shear_denoise_thresholds",
     "shear_inpaint",
+    "shear_inpaint_thresholds",
+    "shear_delta_schedule",
     "shear_profile_enable",
     "shear_profile_read",
     "shear_set_schedule",
@@ -102,6 +105,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).argtypes = [P, P, P, I, P]
     lib.shear_denoise.argtypes = [P, P, P, I, P, P, P]
     lib.shear_inpaint.argtypes = [P, P, P, P, I, P, I, P]
+    lib.shear_denoise_thresholds.argtypes = [P, pD, I, pD, I, ctypes.POINTER(ctypes.c_float)]
+    lib.shear_inpaint_thresholds.argtypes = [P, pD, I, I, ctypes.POINTER(ctypes.c_float)]
+    lib.shear_delta_schedule.argtypes = [I, ctypes.c_double, ctypes.c_double, I, pD]
     for name in EXPORTED:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
@@ -165,6 +171,23 @@ def design_spectra(rows: int, cols: int, n_scales: int, shear_levels: Optional[S
                                     spec.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                     idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int))), "shear_design_spectra")
     return spec[..., 0] + 1j * spec[..., 1], idx
+
+
+def _dptr(a: np.ndarray):
+    """ctypes double* of a contiguous float64 array."""
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def delta_schedule(kind: str, delta_init: float, iterations: int, delta_min: float = 0.0) -> np.ndarray:
+    """Algorithm 3's threshold decay (shear_delta_schedule): kind "geometric" (delta_init to delta_min)
+    or "linear" (delta_init to 0). float64 (iterations,)."""
+    kinds = {"geometric": 0, "linear": 1}
+    if kind not in kinds:
+        raise ValueError(f"kind must be one of {sorted(kinds)}")
+    out = np.empty(int(iterations), dtype=np.float64)
+    _check(load_library().shear_delta_schedule(kinds[kind], float(delta_init), float(delta_min), int(iterations),
+                                               _dptr(out)), "shear_delta_schedule")
+    return out
 
 
 def _stream_ptr(stream) -> ctypes.c_void_p:
@@ -284,21 +307,18 @@ class ShearletSystem:
         return self._inv(self._lib.shear_adjoint, "shear_adjoint", coeffs, out, stream)
 
     # ------------------------------------------------------------ denoising
-    def paper_thresholds(self, sigma: float, factors=None) -> np.ndarray:
-        """Per-filter thresholds of the denoising rule of Section 4.2, delta_k = K_j sigma RMS_k for a
-        filter k of scale j, with K_j = 2.5 except 3.8 on the finest scale unless ``factors`` (J values,
-        coarse to fine) are given; the low-pass (scale 0) gets 0, i.e. is kept. float32 (K,)."""
-        scale = self.idx[:, 1]
-        J = int(scale.max())
-        if factors is None:
-            factors = [2.5] * (J - 1) + [3.8]
-        f = np.asarray(factors, dtype=np.float64)
-        if f.shape != (J,):
-            raise ValueError(f"need {J} scale factors, got shape {f.shape}")
-        t = np.zeros(self.K, dtype=np.float64)
-        band = scale > 0
-        t[band] = f[scale[band] - 1] * float(sigma) * self.rms[band]
-        return t.astype(np.float32)
+    def paper_thresholds(self, sigma, factors=None) -> np.ndarray:
+        """Thresholds of the denoising rule of Section 4.2 (shear_denoise_thresholds): K_j sigma RMS_k for
+        filter k of scale j, the low-pass taking K_1. sigma: a scalar -> float32 (K,), or B values ->
+        (B, K). factors: J values K_1..K_J (coarse to fine), or None for the paper's [2.5, ..., 3.8]."""
+        sig = np.ascontiguousarray(np.atleast_1d(np.asarray(sigma, dtype=np.float64)))
+        out = np.empty((sig.shape[0], self.K), dtype=np.float32)
+        f = None if factors is None else np.ascontiguousarray(factors, dtype=np.float64)
+        _check(self._lib.shear_denoise_thresholds(self._h, _dptr(sig), int(sig.shape[0]),
+                                                  None if f is None else _dptr(f), 0 if f is None else int(f.size),
+                                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "shear_denoise_thresholds")
+        return out[0] if np.ndim(sigma) == 0 else out
 
     def denoise(self, x, thresholds, out=None, kept=False, stream=None):
         """shear_denoise: y = SH^-1 T SH x with hard thresholds (B, K) or (K,) (float32, on x's device).
@@ -329,10 +349,20 @@ class ShearletSystem:
 
     # ------------------------------------------------------------ inpainting
     def inpaint_thresholds(self, deltas, batch: int) -> np.ndarray:
-        """Algorithm 3's per-filter thresholds: thresholds[i][b][k] = deltas[i] * RMS_k. float32 (I, B, K)."""
-        d = np.asarray(deltas, dtype=np.float64).reshape(-1, 1, 1)
-        return np.ascontiguousarray(np.broadcast_to(d * self.rms.reshape(1, 1, -1), (d.shape[0], batch, self.K)),
-                                    dtype=np.float32)
+        """Algorithm 3's per-filter thresholds (shear_inpaint_thresholds): thresholds[i][b][k] =
+        deltas[i] * RMS_k for a schedule of I scalars (every image alike), or deltas[i][b] for an
+        (I, batch) schedule. float32 (I, batch, K)."""
+        d = np.asarray(deltas, dtype=np.float64)
+        if d.ndim == 1:
+            d = np.repeat(d[:, None], batch, axis=1)
+        if d.ndim != 2 or d.shape[1] != batch:
+            raise ValueError(f"deltas must be (iterations,) or (iterations, {batch}), got {d.shape}")
+        d = np.ascontiguousarray(d)
+        out = np.empty((d.shape[0], batch, self.K), dtype=np.float32)
+        _check(self._lib.shear_inpaint_thresholds(self._h, _dptr(d), int(d.shape[0]), int(batch),
+                                                  out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "shear_inpaint_thresholds")
+        return out
 
     def inpaint(self, f_masked, mask, thresholds, out=None, stream=None):
         """shear_inpaint: Algorithm 3 on a batch (B, rows, cols); thresholds (iterations, B, K) float32."""

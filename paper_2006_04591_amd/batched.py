@@ -67,18 +67,17 @@ class UnevenInpainter:
             with torch.cuda.stream(st):
                 fm = torch.stack([f_masked[i] for i in ids]).contiguous()
                 mk = torch.stack([masks[i] for i in ids]).contiguous()
-                thr = []
-                for i in ids:
-                    sch = np.asarray(schedules[i], dtype=np.float64)
-                    if sch.ndim == 1:
-                        sch = sch[:, None] * s.rms[None, :]
-                    if sch.ndim != 2 or sch.shape[1] != s.K:
-                        raise ValueError(f"schedule of image {i} must be (iterations,) or (iterations, {s.K})")
-                    thr.append(sch)
-                its = {t.shape[0] for t in thr}
-                if len(its) != 1:
+                sch = [np.asarray(schedules[i], dtype=np.float64) for i in ids]
+                if len({a.shape[0] for a in sch}) != 1:
                     raise ValueError(f"images of size {key} need the same number of iterations")
-                thr_t = torch.from_numpy(np.ascontiguousarray(np.stack(thr, axis=1), dtype=np.float32)).to(fm.device)
+                if all(a.ndim == 1 for a in sch):
+                    # scalar deltas per iteration and image, weighted per filter by the library
+                    thr = s.inpaint_thresholds(np.stack(sch, axis=1), len(ids))
+                elif all(a.ndim == 2 and a.shape[1] == s.K for a in sch):
+                    thr = np.ascontiguousarray(np.stack(sch, axis=1), dtype=np.float32)
+                else:
+                    raise ValueError(f"schedules of size {key} must all be (iterations,) or all (iterations, {s.K})")
+                thr_t = torch.from_numpy(thr).to(fm.device)
                 y = s.inpaint(fm, mk, thr_t, stream=st)
                 for j, i in enumerate(ids):
                     result[i] = y[j]

@@ -588,6 +588,60 @@ int shear_adjoint(shear_system* s, const float* coeffs, float* x, int batch, voi
     return inverse_like(s, coeffs, x, batch, stream, s ? s->filt_adj : nullptr);
 }
 
+int shear_denoise_thresholds(const shear_system* s, const double* sigma, int batch, const double* factors,
+                             int n_factors, float* out) {
+    if (!s || !sigma || !out) return fail(SHEAR_E_INVALID, "NULL argument");
+    if (batch < 0) return fail(SHEAR_E_INVALID, "batch must not be negative");
+    int J = 0;
+    for (int k = 0; k < s->K; ++k) J = std::max(J, s->idx[(size_t)k * 3 + 1]);
+    if (J < 1) return fail(SHEAR_E_INVALID, "the system's index triples name no scale");
+    std::vector<double> f((size_t)J, 2.5);
+    f[(size_t)J - 1] = 3.8;  // the paper's K_j: 2.5 on every scale but the finest
+    if (factors) {
+        if (n_factors != J)
+            return fail(SHEAR_E_INVALID, "need " + std::to_string(J) + " scale factors, got " + std::to_string(n_factors));
+        f.assign(factors, factors + J);
+    }
+    for (int b = 0; b < batch; ++b)
+        for (int k = 0; k < s->K; ++k) {
+            const int j = std::max(1, s->idx[(size_t)k * 3 + 1]);  // the low-pass (scale 0) takes K_1
+            out[(size_t)b * s->K + k] = (float)(f[(size_t)j - 1] * sigma[b] * s->rms[(size_t)k]);
+        }
+    return SHEAR_OK;
+}
+
+int shear_inpaint_thresholds(const shear_system* s, const double* deltas, int iterations, int batch, float* out) {
+    if (!s || !deltas || !out) return fail(SHEAR_E_INVALID, "NULL argument");
+    if (iterations < 1 || batch < 0) return fail(SHEAR_E_INVALID, "iterations must be positive, batch not negative");
+    for (int i = 0; i < iterations; ++i)
+        for (int b = 0; b < batch; ++b)
+            for (int k = 0; k < s->K; ++k)
+                out[((size_t)i * batch + b) * s->K + k] = (float)(deltas[(size_t)i * batch + b] * s->rms[(size_t)k]);
+    return SHEAR_OK;
+}
+
+int shear_delta_schedule(int kind, double delta_init, double delta_min, int iterations, double* out) {
+    if (!out) return fail(SHEAR_E_INVALID, "out is NULL");
+    if (iterations < 1) return fail(SHEAR_E_INVALID, "iterations must be positive");
+    if (kind == SHEAR_DECAY_GEOMETRIC) {
+        if (!(delta_init > 0.0) || !(delta_min > 0.0))
+            return fail(SHEAR_E_INVALID, "the geometric decay needs delta_init > 0 and delta_min > 0");
+        const double lam = iterations > 1 ? std::pow(delta_min / delta_init, 1.0 / (iterations - 1)) : 1.0;
+        double d = delta_init;
+        for (int i = 0; i < iterations; ++i) {
+            out[i] = d;
+            d *= lam;
+        }
+        return SHEAR_OK;
+    }
+    if (kind == SHEAR_DECAY_LINEAR) {
+        for (int i = 0; i < iterations; ++i)
+            out[i] = iterations > 1 ? delta_init * (1.0 - (double)i / (double)(iterations - 1)) : delta_init;
+        return SHEAR_OK;
+    }
+    return fail(SHEAR_E_INVALID, "unknown decay kind " + std::to_string(kind));
+}
+
 int shear_denoise(shear_system* s, const float* x, float* y, int batch, const float* thresholds, unsigned* kept,
                   void* stream) {
     int rc = check_call(s, x, y, batch, true);

@@ -124,3 +124,24 @@ def test_count_query(P):
     K = ctypes.c_int(0)
     assert lib.shear_design_spectra(ctypes.byref(p), ctypes.byref(K), None, None) == 0
     assert K.value == 49
+
+
+def test_delta_schedule_matches_oracle(P):
+    """Algorithm 3's threshold decay, computed by the library (host only) against the oracle."""
+    from oracle import apps as OA
+
+    for (d0, dmin, it) in [(8.0, 0.5, 5), (250.0, 1.0, 100), (3.0, 1.0, 1), (1.0, 0.01, 50)]:
+        got = P.delta_schedule("geometric", d0, it, dmin)
+        assert np.allclose(got, OA.delta_schedule(d0, dmin, it), rtol=1e-13, atol=0)
+        assert got[0] == d0
+    for (d0, it) in [(120.0, 100), (5.0, 2), (7.0, 1)]:
+        got = P.delta_schedule("linear", d0, it)
+        assert np.allclose(got, OA.delta_schedule_linear(d0, it), rtol=1e-13, atol=1e-13)
+    lib = P.load_library()
+    out = (ctypes.c_double * 4)()
+    assert lib.shear_delta_schedule(0, 1.0, 0.0, 4, out) == -1  # geometric decay needs delta_min > 0
+    assert lib.shear_delta_schedule(7, 1.0, 0.5, 4, out) == -1
+    assert lib.shear_delta_schedule(1, 1.0, 0.0, 0, out) == -1
+    assert lib.shear_delta_schedule(1, 1.0, 0.0, 4, None) == -1
+    assert lib.shear_denoise_thresholds(None, None, 1, None, 0, None) == -1
+    assert lib.shear_inpaint_thresholds(None, None, 1, 1, None) == -1

@@ -48,11 +48,11 @@ def test_thresholds_per_filter(sys128):
     assert t.shape == (s.K,)
     for k, (cone, j, shear) in enumerate(s.idx):
         if j == 0:
-            assert (cone, shear) == (0, 0) and t[k] == 0.0
+            # the low-pass: thresholded like every plane of the listing, with the coarsest scale's factor
+            assert (cone, shear) == (0, 0) and t[k] == pytest.approx(2.5 * sigma * s.rms[k], rel=1e-15)
         else:
             assert t[k] == pytest.approx({1: 2.5, 2: 3.8}[int(j)] * sigma * s.rms[k], rel=1e-15)
-    # the low-pass is the last filter and the only one left untouched
-    assert t[-1] == 0.0 and np.all(t[:-1] > 0)
+    assert np.all(t > 0) and s.idx[-1, 1] == 0
     with pytest.raises(ValueError):
         A.thresholds(s.idx, s.rms, sigma, factors=[1.0])
 
@@ -80,8 +80,12 @@ def test_denoise_constant_image_is_fixed_point(sys128):
     # band-passes vanish on a constant image, so any band thresholds leave it unchanged
     s = sys128
     x = np.full((128, 128), 77.0)
-    y = A.denoise(x, s.spectra, s.W, A.thresholds(s.idx, s.rms, 1e3))
+    t = A.thresholds(s.idx, s.rms, 1e3)
+    t[-1] = 0.0  # keep the low-pass plane, which carries the constant
+    y = A.denoise(x, s.spectra, s.W, t)
     assert np.max(np.abs(y - x)) <= 1e-10
+    # with the low-pass thresholded above the constant every plane is zeroed
+    assert np.max(np.abs(A.denoise(x, s.spectra, s.W, A.thresholds(s.idx, s.rms, 1e3)))) <= 1e-10
 
 
 def test_denoise_improves_psnr(sys128):
@@ -105,7 +109,9 @@ def test_kept_counts_monotone(sys128):
         if prev is not None:
             assert np.all(n <= prev)
         prev = n
-    assert prev[-1] == 128 * 128  # the low-pass plane is kept whole
+    # the counts are the plain number of |c| >= delta per plane
+    d = 4.0 * base
+    assert np.array_equal(prev, [int(np.sum(np.abs(c[k]) >= d[k])) for k in range(s.K)])
 
 
 def test_delta_schedule():

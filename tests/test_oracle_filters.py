@@ -85,6 +85,26 @@ def test_fan_filter_properties():
     assert np.all(P[(b > a)] <= 0.5 + 1e-13)
 
 
+def test_fan_filter_flatness_order():
+    """Maximal flatness of order L = 4 (Section 3.4.1's maxflat design): 1 - P vanishes to order 2L = 8
+    at the pass-band centre (pi, 0) and P to order 8 at the stop-band centre (0, pi). Evaluated by the
+    plain trigonometric sum of the taps: halving the distance divides the deviation by 2^8 (an order-6
+    or order-10 design would give 2^6 or 2^10)."""
+    p = F.default_fan_filter()
+    r = p.shape[0] // 2
+    n = np.arange(-r, r + 1)
+
+    def P(w1, w2):
+        return float(np.real(np.sum(p * np.exp(-1j * (w1 * n[:, None] + w2 * n[None, :])))))
+
+    for a, b in ((1.0, 0.0), (0.6, 0.8), (0.0, 1.0), (0.8, -0.6)):
+        for eps in (0.1, 0.05):
+            dev = [1.0 - P(np.pi + a * e, b * e) for e in (eps, eps / 2)]
+            assert 0.8 * 256 < dev[0] / dev[1] < 1.2 * 256, (a, b, eps, dev)
+            stop = [P(a * e, np.pi + b * e) for e in (eps, eps / 2)]
+            assert 0.8 * 256 < stop[0] / stop[1] < 1.2 * 256, (a, b, eps, stop)
+
+
 # ---------------------------------------------------------------- counts and indices
 
 
@@ -223,14 +243,13 @@ def _embed(kern, N, M):
     return out
 
 
-@pytest.mark.parametrize("N,M,levels", [(128, 128, [1, 1]), (96, 128, [1, 2])])
-def test_spectra_equal_dft_of_spatial_construction(N, M, levels):
+def _spatial_kernels(levels):
+    """Every kernel of a system built spatially, in the filter order: ((cone, j, k), kernel)."""
     J = len(levels)
-    sysx = F.build_system(N, M, J, levels)
     h = F.default_scaling_filter()
     g = F.mirror_filter(h)
     p = F.default_fan_filter()
-    i = 0
+    out = []
     for j in range(1, J + 1):
         s = levels[j - 1]
         U = 2 ** s
@@ -238,14 +257,41 @@ def test_spectra_equal_dft_of_spatial_construction(N, M, levels):
         band = np.convolve(_up(g, 2 ** (lvl - 1), 0), _atrous_low_taps(h, lvl - 1))
         for cone, ks in ((1, range(-U, U + 1)), (2, range(-U + 1, U))):
             for k in ks:
-                d = _spatial_wedge(h, p, s, k)
-                ker = _conv(d, band, 0)
-                if cone == 2:
-                    ker = ker.T
-                ref = np.fft.fft2(_embed(ker, N, M))
-                assert tuple(sysx.idx[i]) == (cone, j, k)
-                assert np.max(np.abs(ref - sysx.spectra[i])) < 1e-12 * max(1.0, np.max(np.abs(ref)))
-                i += 1
+                ker = _conv(_spatial_wedge(h, p, s, k), band, 0)
+                out.append(((cone, j, k), ker.T if cone == 2 else ker))
     low = _atrous_low_taps(h, J)
-    ref = np.fft.fft2(_embed(np.outer(low, low), N, M))
-    assert np.max(np.abs(ref - sysx.spectra[i])) < 1e-12
+    out.append(((0, 0, 0), np.outer(low, low)))
+    return out
+
+
+@pytest.mark.parametrize("N,M,levels", [(128, 128, [1, 1]), (96, 128, [1, 2]), (256, 256, [1, 1, 2]),
+                                        (512, 512, [1, 1, 2, 2])])
+def test_spectra_equal_dft_of_spatial_construction(N, M, levels):
+    """All K filters of the system, the 4-scale [1, 1, 2, 2] system of the 512 x 512 workload included
+    (band-pass levels 3-4 and the level-4 low-pass), against the DFT of the spatial construction."""
+    sysx = F.build_system(N, M, len(levels), levels)
+    kers = _spatial_kernels(levels)
+    assert len(kers) == sysx.K
+    for i, (trip, ker) in enumerate(kers):
+        ref = np.fft.fft2(_embed(ker, N, M))
+        assert tuple(sysx.idx[i]) == trip
+        assert np.max(np.abs(ref - sysx.spectra[i])) < 1e-12 * max(1.0, np.max(np.abs(ref))), trip
+
+
+@pytest.mark.parametrize("levels", [[1, 1], [1, 2], [1, 1, 2], [1, 1, 2, 2], [0, 1, 2], [2, 2, 2, 2, 3]])
+def test_kernel_radii_match_spatial_supports(levels):
+    """kernel_radii (and so system_fits) against the supports of the spatially built kernels: each
+    kernel's array is (2 r0 + 1) x (2 r1 + 1) and its outermost non-zero taps reach both half-widths."""
+    rad = F.kernel_radii(len(levels), levels, 9, (15, 15))
+    kers = _spatial_kernels(levels)
+    assert len(rad) == len(kers)
+    for (cone, j, k, r0, r1), (trip, ker) in zip(rad, kers):
+        assert (cone, j, k) == trip
+        assert ker.shape == (2 * r0 + 1, 2 * r1 + 1), trip
+        nz0, nz1 = np.nonzero(ker)
+        assert np.max(np.abs(nz0 - r0)) == r0 and np.max(np.abs(nz1 - r1)) == r1, trip
+    # a system fits exactly when its widest kernel does
+    w0 = max(2 * r[3] + 1 for r in rad)
+    w1 = max(2 * r[4] + 1 for r in rad)
+    assert F.system_fits(w0, w1, len(levels), levels)
+    assert not F.system_fits(w0 - 1, w1, len(levels), levels) and not F.system_fits(w0, w1 - 1, len(levels), levels)

@@ -26,11 +26,16 @@ def _random_bank(rng, K, N, M):
 
 
 @pytest.mark.parametrize("n", list(range(1, 12)))
-def test_tfftshift_matches_numpy(n):
+def test_centring_matches_numpy(n):
+    """The centred layout of Section 3.3 is numpy's fftshift (ifftshift undoes it), even and odd n."""
     x = np.arange(n * (n + 3)).reshape(n, n + 3).astype(float)
-    assert np.array_equal(T.tfftshift(x), np.fft.fftshift(x))
-    assert np.array_equal(T.itfftshift(x), np.fft.ifftshift(x))
-    assert np.array_equal(T.itfftshift(T.tfftshift(x)), x)
+    assert np.array_equal(T.to_centred(x), np.fft.fftshift(x))
+    assert np.array_equal(T.from_centred(x), np.fft.ifftshift(x))
+    assert np.array_equal(T.from_centred(T.to_centred(x)), x)
+    # zero frequency (natural index 0) sits at index floor(n/2) of each centred axis
+    d = np.zeros((n, n + 3))
+    d[0, 0] = 1.0
+    assert T.to_centred(d)[n // 2, (n + 3) // 2] == 1.0
 
 
 @pytest.mark.parametrize("N,M", [(16, 16), (15, 17), (8, 13)])
