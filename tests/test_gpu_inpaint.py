@@ -224,3 +224,29 @@ def test_inpaint_uneven_full_sizes(gpu):
     torch.cuda.synchronize()
     assert _rel(y.cpu().numpy(), want) <= TOL
     inp.close()
+
+
+@pytest.mark.parametrize("n", [512, 1024])
+def test_inpaint_uneven_sizes_match_oracle(gpu, n):
+    """The 512 x 512 and 1024 x 1024 members of the uneven workload (49 filters) through the uneven
+    inpainter, five iterations against the oracle with gap thresholds, next to a 256 x 256 image."""
+    from paper_2006_04591_amd import UnevenInpainter
+
+    _say(f"case: uneven inpainting, {n}x{n} against the oracle, 5 iterations")
+    refs = {256: OF.build_system(256, 256, 3), n: OF.build_system(n, n, 4)}
+    inp = UnevenInpainter()
+    fms, ms, schedules, wants = [], [], [], []
+    for i, sz in enumerate((n, 256)):
+        f = synth.cartoon(sz, sz, seed=3700 + i)
+        m = synth.random_mask(sz, sz, 0.5, seed=3750 + i)
+        fm = (f * m).astype(np.float32)
+        rows, y = oracle_schedule(refs[sz], fm, m, OA.delta_schedule(_d0(refs[sz], fm), 2.0, 5))
+        fms.append(_to(fm, gpu))
+        ms.append(_to(m, gpu))
+        schedules.append(rows)
+        wants.append(y)
+    out = inp.run(fms, ms, schedules)
+    torch.cuda.synchronize()
+    for i in range(2):
+        assert _rel(out[i].cpu().numpy(), wants[i]) <= TOL
+    inp.close()

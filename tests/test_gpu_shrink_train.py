@@ -2,10 +2,10 @@
 forward, loss epilogue, backward-data and weight-gradient kernels) against the
 oracle's analytic gradients (bfloat16 rounding at the same points; the oracle's
 gradients are pinned by FP64 finite differences). Gradients are compared in
-relative L2 per parameter tensor within 2e-2: the gradient planes are stored
-in bfloat16 (relative rounding 2^-9), and values that round to a different
-bfloat16 on the two sides, because their FP32 and FP64 sums differ, add a
-little more."""
+relative L2 per parameter tensor within 1e-3, the loss within 1e-3 relative:
+both sides round to bfloat16 at the same points, so what differs is FP32
+against FP64 accumulation and the few values that round to a different
+bfloat16 because of it (measured about 1e-4)."""
 import numpy as np
 import pytest
 
@@ -72,11 +72,11 @@ def test_train_step_gradients_match_oracle(gpu):
         loss = net.train_step(_to(cn, gpu), _to(cc, gpu), _to(sig, gpu), lr=0.0, temperature=T)
         torch.cuda.synchronize()
         assert torch.equal(net.flat, before)  # a zero rate leaves the parameters alone
-        assert abs(float(loss) - L) <= 1e-2 * L
+        assert abs(float(loss) - L) <= 1e-3 * L
         for n in want:
             e = _rel(net.grad(n).cpu().numpy(), want[n])
             print(f"grad {n}: rel L2 {e:.2e}")
-            assert e <= 2e-2, n
+            assert e <= 1e-3, n
 
 
 def test_training_reduces_loss(gpu):
@@ -130,8 +130,8 @@ def test_train_step_gradients_wide_channel_counts(gpu, K):
         net = ShrinkNet(s, {n: getattr(p, n) for n in ShrinkNet.NAMES})
         loss = net.train_step(_to(cn, gpu), _to(cc, gpu), _to(sig, gpu), lr=0.0, temperature=T)
         torch.cuda.synchronize()
-        assert abs(float(loss) - L) <= 1e-2 * L
+        assert abs(float(loss) - L) <= 1e-3 * L
         for n in want:
             e = _rel(net.grad(n).cpu().numpy(), want[n])
             print(f"grad {n}: rel L2 {e:.2e}")
-            assert e <= 2e-2, n
+            assert e <= 1e-3, n
