@@ -63,8 +63,6 @@ def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
         "cols_inv": filt,
         "rows_c2r_images": img,
         "rows_thresh": 0,
-        "image_spectra": 0,
-        "plane_fwd": filt + coef,
     }[kind]
 
 
@@ -80,8 +78,6 @@ def exchange_bytes(kind: str, K: int) -> float:
         "cols_inv": B * K * plane + B * plane,
         "rows_c2r_images": B * plane,
         "rows_thresh": 2 * B * K * plane,
-        "image_spectra": 2 * B * plane,
-        "plane_fwd": B * plane,
     }.get(kind, 0.0)
 
 
@@ -484,8 +480,6 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle baseline sample length (0 = skip)")
-    ap.add_argument("--forward-path", default="", choices=("", "plane", "exchange"),
-                    help="forward execution path (default: the library's choice for the size)")
     ap.add_argument("--chunk-images", type=int, default=0,
                     help="images per chunk of the K-expanded intermediate (0 = whole batch)")
     ap.add_argument("--train-steps", type=int, default=1250, help="shrink: training steps (16 pairs each)")
@@ -533,8 +527,6 @@ def main() -> int:
         cap = B * pb + args.chunk_images * 49 * pb
     shs = ShearletSystem.build(N, M, J, max_workspace_bytes=cap)
     build_s = time.perf_counter() - t0
-    if args.forward_path:
-        shs.set_paths(args.forward_path)
     K = shs.K
     S, _ = shs.export_spectra()
     real_filters = bool(np.all(S.imag == 0))

@@ -263,9 +263,7 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
 #define SHEAR_KERNEL_COLS_INV 4        /* inverse/adjoint: column FFT, x filter, sum over k, IFFT */
 #define SHEAR_KERNEL_ROWS_C2R_IMAGES 5 /* inverse/adjoint: row inverse FFT -> images   */
 #define SHEAR_KERNEL_ROWS_THRESH 6     /* denoising: row inverse FFT, hard threshold, row FFT (in place) */
-#define SHEAR_KERNEL_IMAGE_SPECTRA 7   /* forward, on-chip path: column FFT of the images' row spectra */
-#define SHEAR_KERNEL_PLANE_FWD 8       /* forward, on-chip path: filter, column IFFT and row c2r of a plane block */
-#define SHEAR_KERNEL_KINDS 9
+#define SHEAR_KERNEL_KINDS 7
 
 /* Per-launch timing (tracing). While enabled, every kernel launch of the
  * system is bracketed by two hipEvents recorded on the caller's stream. */
@@ -275,24 +273,6 @@ int shear_profile_enable(shear_system* s, int on);
  * and their summed duration in ms (arrays of SHEAR_KERNEL_KINDS) since the
  * previous read, and clears the record. */
 int shear_profile_read(shear_system* s, int* launches, double* total_ms);
-
-/* Execution path of shear_forward (Algorithm 1, Section 3.4.2).
- *   SHEAR_PATH_EXCHANGE: column stage and row stage of every (image, filter)
- *     plane in separate launches, through an intermediate plane in device
- *     memory (any supported size).
- *   SHEAR_PATH_PLANE (the default where supported: rows, cols in
- *     {128, 256, 512}, not 512 x 128): the image spectra are formed once, then
- *     one workgroup per (image, filter, residue r < D) computes the
- *     coefficient rows n1 = D m + r of a plane entirely on chip; D = 1 up to
- *     N x M/2 = 32768, else the column inverse FFT is decimated in frequency
- *     (D = 2 or 4). Only the coefficients are written. Its workspace is two
- *     planes per image; when that exceeds the workspace cap the exchange
- *     path runs instead.
- * Both compute the same transform; results agree to rounding.
- * SHEAR_E_SIZE for the on-chip path at an unsupported size. */
-#define SHEAR_PATH_EXCHANGE 0
-#define SHEAR_PATH_PLANE 1
-int shear_set_paths(shear_system* s, int forward_path);
 
 /* Column-pass schedule of the separate-launch kernels: pw_fwd / pw_inv
  * columns per block (16 or 8; 16 needs cols >= 32) and kg_fwd / kg_inv

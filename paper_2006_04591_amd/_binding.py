@@ -42,7 +42,6 @@ EXPORTED = (
     "shear_delta_schedule",
     "shear_profile_enable",
     "shear_profile_read",
-    "shear_set_paths",
     "shear_set_schedule",
     "shear_autotune",
     "shear_shrink_params_bytes",
@@ -113,7 +112,6 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
     lib.shear_set_schedule.argtypes = [P, I, I, I, I]
-    lib.shear_set_paths.argtypes = [P, I]
     lib.shear_shrink_params_bytes.argtypes = [I, ctypes.POINTER(ctypes.c_size_t)]
     lib.shear_shrink_pack.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.shear_shrink_apply.argtypes = [P, P, P, P, I, P, P, P]
@@ -386,14 +384,7 @@ class ShearletSystem:
         self._keep = thr
         return out
 
-    # ------------------------------------------------------------ execution path and column-pass schedule
-    PATHS = {"exchange": 0, "plane": 1}
-
-    def set_paths(self, forward: str) -> None:
-        """Execution path of the forward transform (shear_set_paths): "plane" (on chip, the default where
-        supported) or "exchange" (column and row stages through an intermediate plane)."""
-        _check(self._lib.shear_set_paths(self._h, self.PATHS[forward]), "shear_set_paths")
-
+    # ------------------------------------------------------------ column-pass schedule
     def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0, kg_fwd: int = 0, kg_inv: int = 0) -> None:
         """Columns per block and filter groups of the forward and inverse column passes (shear_set_schedule);
         0 keeps a value."""
@@ -409,7 +400,7 @@ class ShearletSystem:
 
     # ------------------------------------------------------------ tracing
     KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images",
-                    "rows_thresh", "image_spectra", "plane_fwd")
+                    "rows_thresh")
 
     def profile(self, on: bool = True) -> None:
         """Brackets every launch with hipEvents on the caller's stream (shear_profile_enable)."""

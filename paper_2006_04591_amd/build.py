@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libshear.so")
-SOURCES = ["builder.cpp", "shear_api.cpp", "kernels.hip", "plane.hip", "shrink.hip"]
+SOURCES = ["builder.cpp", "shear_api.cpp", "kernels.hip", "shrink.hip"]
 
 FLAGS = [
     "-O3",

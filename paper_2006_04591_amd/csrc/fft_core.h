@@ -202,7 +202,7 @@ __device__ __forceinline__ int xmap(int a) {
     }
 }
 
-template <int L, int P, bool INV, int NS, bool FIRST, int TWS = 1>
+template <int L, int P, bool INV, int NS, bool FIRST>
 struct FFTPass {
     static __device__ __forceinline__ void run(float2 (&v)[P], float2* s, int t, const float2* __restrict__ tw) {
         constexpr int T = L / P;
@@ -232,7 +232,7 @@ struct FFTPass {
                 const int kk = j & (NS - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    float2 tv = tw[TWS * r * kk * (L / (NS * R))];
+                    float2 tv = tw[r * kk * (L / (NS * R))];
                     if (INV) tv.y = -tv.y;
                     w[r] = cmul(w[r], tv);
                 }
@@ -247,30 +247,17 @@ struct FFTPass {
                 for (int r = 0; r < R; ++r) s[xmap<NS, R>(idxD + r * NS)] = w[r];
             }
         }
-        if constexpr (!LAST) FFTPass<L, P, INV, NS * R, false, TWS>::run(v, s, t, tw);
+        if constexpr (!LAST) FFTPass<L, P, INV, NS * R, false>::run(v, s, t, tw);
     }
 };
 
-// TWS: stride of the twiddle table, which holds exp(-2 pi i m / (TWS L)), m < TWS L (a table made
-// for a TWS times longer transform serves every shorter one).
-template <int L, int P, bool INV, int TWS = 1>
+template <int L, int P, bool INV>
 __device__ __forceinline__ void fft(float2 (&v)[P], float2* s, int t, const float2* __restrict__ tw) {
-    FFTPass<L, P, INV, 1, true, TWS>::run(v, s, t, tw);
+    FFTPass<L, P, INV, 1, true>::run(v, s, t, tw);
 }
 
 template <bool REAL>
 __device__ __forceinline__ float2 fmul(const void* __restrict__ f, size_t i, float2 a) {
-    if constexpr (REAL) {
-        return cscale(a, reinterpret_cast<const float*>(f)[i]);
-    } else {
-        return cmul(a, reinterpret_cast<const float2*>(f)[i]);
-    }
-}
-
-// as fmul with a 32-bit element offset from a block-uniform base (one 32-bit address register
-// per lane instead of two)
-template <bool REAL>
-__device__ __forceinline__ float2 fmul32(const void* __restrict__ f, unsigned i, float2 a) {
     if constexpr (REAL) {
         return cscale(a, reinterpret_cast<const float*>(f)[i]);
     } else {

@@ -64,18 +64,6 @@ hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nim
 
 bool size_supported(int n);
 
-// ---------------------------------------------------------------- on-chip forward (plane.hip)
-// Rows, columns in {128, 256, 512} except 512 x 128. One workgroup per (image, filter, residue
-// r < D) computes the coefficient rows n1 = D m + r of one plane from the image spectrum:
-// D = plane_fwd_decimation(N, M) (1 when N x M/2 <= 32768, else N M / 65536).
-bool plane_fwd_supported(int N, int M);
-int plane_fwd_decimation(int N, int M);
-// Xh (nimg x L x N float2, column-major per image) = scale * colFFT(A) (A in the panel layout).
-hipError_t launch_image_spectra(const DevPlan& d, const float2* A, float2* Xh, int nimg, float scale, hipStream_t st);
-// out (nimg x K x N x M) = coefficients Re colIFFT-then-row-c2r (filt_k (.) Xh).
-hipError_t launch_plane_fwd(const DevPlan& d, const float2* Xh, float* out, int nimg, const void* filt,
-                            hipStream_t st);
-
 // Fills n words with zero (a kernel, so that the fill can be captured in a graph).
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 

@@ -47,7 +47,6 @@ struct shear_system {
     };
     std::vector<Rec> prof;
     int cus = 0;  // compute units of the device
-    int fwd_path = SHEAR_PATH_EXCHANGE;  // shear_set_paths; set to the on-chip path where supported
     // inpainting: the whole iteration sequence of the last call shape, captured as one HIP graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -218,7 +217,6 @@ int finish_system(shear_system* s, std::string& why) {
         why = std::string("querying the compute-unit count failed: ") + hipGetErrorString(e);
         return SHEAR_E_HIP;
     }
-    s->fwd_path = shear::plane_fwd_supported(N, M) ? SHEAR_PATH_PLANE : SHEAR_PATH_EXCHANGE;
     return SHEAR_OK;
 }
 
@@ -375,32 +373,6 @@ int inverse_like(shear_system* s, const float* coeffs, float* x, int batch, void
     hipError_t e = timed(s, SHEAR_KERNEL_ROWS_C2R_IMAGES, st,
                          [&] { return shear::launch_rows_c2r(d, V, x, batch, 1.0f, false, st); });
     if (e != hipSuccess) return hip_fail(e, "row c2r launch");
-    return SHEAR_OK;
-}
-
-// On-chip forward path: [A: batch row-spectrum planes][Xh: batch image spectra]
-size_t plane_fwd_ws(const shear_system* s, int batch) { return 2 * (size_t)batch * plane_bytes(s); }
-
-bool plane_fwd_usable(const shear_system* s, int batch) {
-    return s->fwd_path == SHEAR_PATH_PLANE && shear::plane_fwd_supported(s->rows, s->cols) &&
-           plane_fwd_ws(s, batch) <= s->ws_cap;
-}
-
-int forward_plane(shear_system* s, const float* x, float* coeffs, int batch, hipStream_t st) {
-    int rc = ensure_ws(s, plane_fwd_ws(s, batch));
-    if (rc != SHEAR_OK) return rc;
-    const shear::DevPlan& d = s->plan;
-    const size_t pb = plane_bytes(s) / sizeof(float2);
-    float2* A = (float2*)s->ws;
-    float2* Xh = A + (size_t)batch * pb;
-    const float scale = (float)(1.0 / ((double)d.N * d.M));  // 1/(N M): a power of two, exact
-    hipError_t e = timed(s, SHEAR_KERNEL_ROWS_R2C_IMAGES, st,
-                         [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
-    if (e != hipSuccess) return hip_fail(e, "row r2c launch");
-    e = timed(s, SHEAR_KERNEL_IMAGE_SPECTRA, st, [&] { return shear::launch_image_spectra(d, A, Xh, batch, scale, st); });
-    if (e != hipSuccess) return hip_fail(e, "image spectra launch");
-    e = timed(s, SHEAR_KERNEL_PLANE_FWD, st, [&] { return shear::launch_plane_fwd(d, Xh, coeffs, batch, s->filt_fwd, st); });
-    if (e != hipSuccess) return hip_fail(e, "plane forward launch");
     return SHEAR_OK;
 }
 
@@ -568,7 +540,6 @@ int shear_workspace_bytes(const shear_system* s, int batch, size_t* bytes) {
     const int chunk = chunk_images(s, batch);
     if (chunk < 1) return fail(SHEAR_E_NOMEM, "workspace cap too small for one image");
     need = ws_needed(s, batch, chunk);
-    if (plane_fwd_usable(s, batch)) need = std::max(need, plane_fwd_ws(s, batch));
     *bytes = need;
     return SHEAR_OK;
 }
@@ -584,7 +555,6 @@ int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, voi
     int rc = check_call(s, x, coeffs, batch, true);
     if (rc == EMPTY_CALL) return SHEAR_OK;
     if (rc != SHEAR_OK) return rc;
-    if (plane_fwd_usable(s, batch)) return forward_plane(s, x, coeffs, batch, (hipStream_t)stream);
     int chunk = 0;
     if ((rc = prepare_ws(s, batch, chunk)) != SHEAR_OK) return rc;
     const shear::DevPlan& d = s->plan;
@@ -805,16 +775,6 @@ int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, flo
         s->graph_key = key;
     }
     if ((e = hipGraphLaunch(s->gexec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
-    return SHEAR_OK;
-}
-
-int shear_set_paths(shear_system* s, int forward_path) {
-    if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
-    if (forward_path != SHEAR_PATH_EXCHANGE && forward_path != SHEAR_PATH_PLANE)
-        return fail(SHEAR_E_INVALID, "unknown path " + std::to_string(forward_path));
-    if (forward_path == SHEAR_PATH_PLANE && !shear::plane_fwd_supported(s->rows, s->cols))
-        return fail(SHEAR_E_SIZE, "the on-chip forward path needs rows, cols in {128, 256, 512} (not 512 x 128)");
-    s->fwd_path = forward_path;
     return SHEAR_OK;
 }
 

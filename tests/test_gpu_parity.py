@@ -441,58 +441,6 @@ def test_config4_256_k33_b32_sampled(gpu, lib):
             assert _rel(a[b].cpu().numpy(), OT.adjoint_plain(g[b].astype(np.float64), ref.spectra)) <= TOL
 
 
-# ---------------------------------------------------------------- forward execution paths
-
-
-@pytest.mark.parametrize("N,M,J,B", [(128, 128, 2, 3), (128, 256, 2, 2), (128, 512, 2, 8), (256, 128, 2, 2),
-                                     (256, 256, 3, 8), (256, 256, 3, 5), (256, 512, 3, 3), (512, 256, 3, 8),
-                                     (512, 512, 4, 16), (512, 512, 4, 3)])
-def test_forward_paths_agree(gpu, lib, N, M, J, B):
-    """The on-chip forward (one workgroup per plane block; the column IFFT decimated in frequency by
-    D = 2 at 256 x 512 and 512 x 256, by 4 at 512 x 512) against the exchange path and the oracle,
-    whole tensors, at batches that take the XCD-grouped task order (multiples of 8) and the plain one."""
-    from paper_2006_04591_amd import ShearletSystem
-
-    _say(f"case: forward paths {N}x{M} J={J} B={B}")
-    ref = OF.build_system(N, M, J)
-    x = synth.cartoon_batch(B, N, M, config=6, sigma=10.0)
-    with ShearletSystem.build(N, M, J) as s:
-        xg = _to(x, gpu)
-        s.set_paths("plane")
-        s.profile(True)
-        cp = s.forward(xg)
-        rec = s.profile_read()
-        s.profile(False)
-        s.set_paths("exchange")
-        ce = s.forward(xg)
-        s.set_paths("plane")
-        torch.cuda.synchronize()
-        assert rec["plane_fwd"][0] == 1 and rec["cols_fwd"][0] == 0
-        assert _rel(cp.cpu().numpy(), ce.cpu().numpy()) <= 1e-6
-        num = den = 0.0
-        for b in range(B):
-            want = OT.forward_plain(x[b].astype(np.float64), ref.spectra)
-            num += float(np.sum((cp[b].double().cpu().numpy() - want) ** 2))
-            den += float(np.sum(want ** 2))
-        assert np.sqrt(num / den) <= TOL
-
-
-def test_forward_path_user_banks(gpu, lib):
-    """The on-chip forward with complex (non-real) and real user spectra, against the oracle."""
-    from paper_2006_04591_amd import ShearletSystem
-
-    for (N, M, K, real, B) in [(256, 256, 3, False, 2), (512, 512, 2, False, 1), (128, 512, 4, True, 3)]:
-        _say(f"case: on-chip forward, user bank {N}x{M} K={K} real={real}")
-        rng = np.random.default_rng(N + M + K)
-        S = _random_bank(rng, K, N, M, real)
-        x = rng.standard_normal((B, N, M)).astype(np.float32)
-        with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
-            c = s.forward(_to(x, gpu))
-            torch.cuda.synchronize()
-            for b in range(B):
-                assert _rel(c[b].cpu().numpy(), OT.forward_plain(x[b].astype(np.float64), S)) <= TOL
-
-
 # ---------------------------------------------------------------- column-pass schedules and the autotuner
 
 
