@@ -128,6 +128,21 @@ int shear_workspace_bytes(const shear_system* s, int batch, size_t* bytes);
  * hip_stream (a hipStream_t, NULL = default). x and coeffs must not overlap. */
 int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, void* hip_stream);
 
+/* shear_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same transform, bitwise equal to shear_forward, computed through a fixed
+ * 64 MiB device scratch array that the library holds on each GPU it runs on
+ * until the process ends, instead of the system's workspace. It calls no
+ * hipMalloc, hipFree or other allocating routine and never synchronises.
+ * Images are processed in chunks of as many as fit: one image needs (K + 1)
+ * planes of rows x cols/2 complex values (K + 1 = 50 planes, 50 MiB, at
+ * 512 x 512 with 49 filters); SHEAR_E_SIZE when one image needs more than the
+ * scratch holds (e.g. 1024 x 1024 with 49 filters). Every call on a GPU shares
+ * that GPU's scratch: calls that overlap on one GPU (other streams, other
+ * systems, other threads) race and must be ordered by the caller.
+ * Asynchronous on hip_stream. */
+int shear_forward_noalloc(shear_system* s, const float* x, float* coeffs, int batch, void* hip_stream);
+
 /* tfshearrec2D / Algorithm 2 (Section 3.4.2): coeffs -> x, dividing the
  * filtered sum by the dual-frame weight W. Asynchronous. */
 int shear_inverse(shear_system* s, const float* coeffs, float* x, int batch, void* hip_stream);

@@ -33,6 +33,7 @@ EXPORTED = (
     "shear_reserve",
     "shear_workspace_bytes",
     "shear_forward",
+    "shear_forward_noalloc",
     "shear_inverse",
     "shear_adjoint",
     "shear_denoise",
@@ -101,7 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shear_export_spectra.argtypes = [P, pD, pD]
     lib.shear_reserve.argtypes = [P, I]
     lib.shear_workspace_bytes.argtypes = [P, I, ctypes.POINTER(ctypes.c_size_t)]
-    for name in ("shear_forward", "shear_inverse", "shear_adjoint"):
+    for name in ("shear_forward", "shear_forward_noalloc", "shear_inverse", "shear_adjoint"):
         getattr(lib, name).argtypes = [P, P, P, I, P]
     lib.shear_denoise.argtypes = [P, P, P, I, P, P, P]
     lib.shear_inpaint.argtypes = [P, P, P, P, I, P, I, P]
@@ -285,6 +286,16 @@ class ShearletSystem:
         self._check_tensor(out, (B, self.K, self.rows, self.cols), "out")
         _check(self._lib.shear_forward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()), B,
                                        _stream_ptr(stream)), "shear_forward")
+        return out
+
+    def forward_noalloc(self, x, out):
+        """shear_forward_noalloc: as forward, through the library's fixed device scratch (no allocation in
+        the call); ``out`` (B, K, rows, cols) must be given."""
+        B = x.shape[0]
+        self._check_tensor(x, (B, self.rows, self.cols), "x")
+        self._check_tensor(out, (B, self.K, self.rows, self.cols), "out")
+        _check(self._lib.shear_forward_noalloc(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                               B, _stream_ptr(None)), "shear_forward_noalloc")
         return out
 
     def _inv(self, fn, name, c, out, stream):

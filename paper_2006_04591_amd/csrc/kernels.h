@@ -67,4 +67,9 @@ bool size_supported(int n);
 // Fills n words with zero (a kernel, so that the fill can be captured in a graph).
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st);
 
+// Size of the fixed device scratch of the allocation-free forward (one copy per device).
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+// Device address of that scratch on the current device (looked up once per device).
+hipError_t static_scratch(void** ptr);
+
 }  // namespace shear

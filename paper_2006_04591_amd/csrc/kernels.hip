@@ -12,6 +12,7 @@
 #include "fft_core.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace shear {
 namespace {
@@ -854,6 +855,33 @@ hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {
     const int blocks = std::max(1, std::min(1024, (n + threads - 1) / threads));
     hipLaunchKernelGGL(k_zero_u32, dim3(blocks), dim3(threads), 0, st, p, n);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- fixed scratch (allocation-free forward)
+// A file-scope device array, one copy per GPU the library runs on, held until the process ends. Host
+// code never passes the array's name to a kernel: it is a host-side stand-in, not a device address.
+// The device address comes from hipGetSymbolAddress, taken once per device with that device current.
+namespace {
+__device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t static_scratch(void** ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace shear

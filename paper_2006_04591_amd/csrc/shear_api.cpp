@@ -580,6 +580,39 @@ int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, voi
     return SHEAR_OK;
 }
 
+int shear_forward_noalloc(shear_system* s, const float* x, float* coeffs, int batch, void* stream) {
+    int rc = check_call(s, x, coeffs, batch, true);
+    if (rc == EMPTY_CALL) return SHEAR_OK;
+    if (rc != SHEAR_OK) return rc;
+    const shear::DevPlan& d = s->plan;
+    const size_t pb = plane_bytes(s);
+    const size_t per_image = (size_t)(d.K + 1) * pb;  // row spectra of the image + its K exchange planes
+    if (per_image > shear::kStaticScratchBytes)
+        return fail(SHEAR_E_SIZE, "shear_forward_noalloc: one image needs " + std::to_string(per_image) +
+                                      " bytes of scratch (K + 1 planes of " + std::to_string(pb) +
+                                      " bytes), the fixed scratch holds " +
+                                      std::to_string(shear::kStaticScratchBytes));
+    void* base = nullptr;
+    hipError_t e = shear::static_scratch(&base);
+    if (e != hipSuccess) return hip_fail(e, "locating the fixed scratch");
+    hipStream_t st = (hipStream_t)stream;
+    const int chunk = (int)std::min<size_t>((size_t)batch, shear::kStaticScratchBytes / per_image);
+    const size_t img = (size_t)d.N * d.M;
+    const float scale = (float)(1.0 / (double)img);  // 1/(N M): a power of two, exact
+    for (int b0 = 0; b0 < batch; b0 += chunk) {
+        const int nb = std::min(chunk, batch - b0);
+        float2* A = (float2*)base;
+        float2* T = (float2*)((char*)base + (size_t)nb * pb);
+        e = shear::launch_rows_r2c(d, x + (size_t)b0 * img, A, nb, false, st);
+        if (e != hipSuccess) return hip_fail(e, "row r2c launch");
+        e = shear::launch_cols_fwd(d, A, T, nb, s->filt_fwd, scale, st);
+        if (e != hipSuccess) return hip_fail(e, "column pass launch");
+        e = shear::launch_rows_c2r(d, T, coeffs + (size_t)b0 * d.K * img, nb * d.K, 1.0f, true, st);
+        if (e != hipSuccess) return hip_fail(e, "row c2r launch");
+    }
+    return SHEAR_OK;
+}
+
 int shear_inverse(shear_system* s, const float* coeffs, float* x, int batch, void* stream) {
     return inverse_like(s, coeffs, x, batch, stream, s ? s->filt_inv : nullptr);
 }
