@@ -26,7 +26,7 @@
  *   shears -(2^s-1)..(2^s-1), s = shear level of scale j; low-pass last.
  *   Index triples are (cone, scale, shear); the low-pass is (0, 0, 0).
  *
- * Sizes: the GPU path takes rows, cols powers of two in [16, 1024].
+ * Sizes: the GPU path takes rows, cols powers of two in [16, 2048].
  *
  * Ownership and ordering
  *   The caller owns x / coeffs (device memory, e.g. torch tensors) and keeps

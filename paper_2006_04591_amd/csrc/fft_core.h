@@ -171,7 +171,7 @@ __device__ __forceinline__ void dft(float2* v) {
 }
 
 // ---------------------------------------------------------------- wave-level sync
-// Every FFT group (T = L/P <= 64 threads, aligned) lives inside one wavefront,
+// An FFT group of T = L/P <= 64 threads (aligned) lives inside one wavefront,
 // and its LDS scratch is private to the group. LDS operations of a wavefront
 // execute in issue order, so ordering the group's LDS writes before its reads
 // needs only a compiler-level fence, not a workgroup barrier.
@@ -179,6 +179,18 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A group of more than 64 threads (the 2048-point column FFTs: 128 threads of 16 points) spans
+// several wavefronts and synchronises with a workgroup barrier; every thread of such a block runs
+// the same FFT calls, so all of them reach every barrier.
+template <int T>
+__device__ __forceinline__ void group_sync() {
+    if constexpr (T <= 64) {
+        wave_sync();
+    } else {
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- Stockham FFT
@@ -214,13 +226,12 @@ struct FFTPass {
 #pragma unroll
             for (int q = 0; q < P; ++q) u[q] = v[q];
         } else {
-            static_assert(T <= 64, "an FFT group must fit in one wavefront");
-            wave_sync();
+            group_sync<T>();
 #pragma unroll
             for (int i = 0; i < BPT; ++i)
 #pragma unroll
                 for (int r = 0; r < R; ++r) u[i + BPT * r] = s[xmap<NS / P, P>((t + T * i) + r * (L / R))];
-            wave_sync();
+            group_sync<T>();
         }
 #pragma unroll
         for (int i = 0; i < BPT; ++i) {

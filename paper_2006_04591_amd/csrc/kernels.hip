@@ -26,7 +26,8 @@ struct Pts {
 };
 
 // points per thread of the column FFTs (N-point): 8 up to N = 512 (256-point columns use two
-// 32-thread groups per wavefront), 16 at N = 1024
+// 32-thread groups per wavefront), 16 at N = 1024 and 2048 (a 2048-point group is 128 threads, two
+// wavefronts that synchronise with workgroup barriers)
 template <int N>
 struct ColPts {
     static constexpr int value = (N >= 1024) ? 16 : 8;
@@ -745,7 +746,9 @@ hipError_t cols_inv_t(const DevPlan& d, const float2* U, float2* V, int nimg, co
 
 }  // namespace
 
-bool size_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024; }
+bool size_supported(int n) {
+    return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
+}
 
 template <int TAG>
 hipError_t rows_r2c_sw(const DevPlan& d, const float* in, float2* out, int planes, hipStream_t st) {
@@ -757,6 +760,7 @@ hipError_t rows_r2c_sw(const DevPlan& d, const float* in, float2* out, int plane
         case 256: return rows_r2c_t<256, TAG>(d, in, out, planes, st);
         case 512: return rows_r2c_t<512, TAG>(d, in, out, planes, st);
         case 1024: return rows_r2c_t<1024, TAG>(d, in, out, planes, st);
+        case 2048: return rows_r2c_t<2048, TAG>(d, in, out, planes, st);
     }
     return hipErrorInvalidValue;
 }
@@ -771,6 +775,7 @@ hipError_t rows_c2r_sw(const DevPlan& d, const float2* in, float* out, int plane
         case 256: return rows_c2r_t<256, TAG>(d, in, out, planes, scale, st);
         case 512: return rows_c2r_t<512, TAG>(d, in, out, planes, scale, st);
         case 1024: return rows_c2r_t<1024, TAG>(d, in, out, planes, scale, st);
+        case 2048: return rows_c2r_t<2048, TAG>(d, in, out, planes, scale, st);
     }
     return hipErrorInvalidValue;
 }
@@ -795,6 +800,7 @@ hipError_t launch_rows_r2c_mix(const DevPlan& d, const float* fm, const float* m
         case 256: return rows_r2c_mix_t<256>(d, fm, mask, f, out, planes, st);
         case 512: return rows_r2c_mix_t<512>(d, fm, mask, f, out, planes, st);
         case 1024: return rows_r2c_mix_t<1024>(d, fm, mask, f, out, planes, st);
+        case 2048: return rows_r2c_mix_t<2048>(d, fm, mask, f, out, planes, st);
     }
     return hipErrorInvalidValue;
 }
@@ -809,6 +815,7 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
         case 256: return rows_thresh_t<256>(d, planes, nplanes, thr, kept, st);
         case 512: return rows_thresh_t<512>(d, planes, nplanes, thr, kept, st);
         case 1024: return rows_thresh_t<1024>(d, planes, nplanes, thr, kept, st);
+        case 2048: return rows_thresh_t<2048>(d, planes, nplanes, thr, kept, st);
     }
     return hipErrorInvalidValue;
 }
@@ -826,6 +833,7 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
             case 256: return FN<256, 16>(__VA_ARGS__);                             \
             case 512: return FN<512, 16>(__VA_ARGS__);                             \
             case 1024: return FN<1024, 16>(__VA_ARGS__);                           \
+            case 2048: return FN<2048, 4>(__VA_ARGS__);                            \
         }                                                                          \
     } else if (d.L >= 8) {                                                         \
         switch (d.N) {                                                             \
@@ -836,6 +844,7 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
             case 256: return FN<256, 8>(__VA_ARGS__);                              \
             case 512: return FN<512, 8>(__VA_ARGS__);                              \
             case 1024: return FN<1024, PW8_1024>(__VA_ARGS__);                     \
+            case 2048: return FN<2048, 4>(__VA_ARGS__);                            \
         }                                                                          \
     }                                                                              \
     return hipErrorInvalidValue;

@@ -240,7 +240,7 @@ int new_system(int rows, int cols, size_t cap, shear_system** out, shear_system*
     if (!out) return fail(SHEAR_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!shear::size_supported(rows) || !shear::size_supported(cols))
-        return fail(SHEAR_E_SIZE, "GPU path needs rows and cols powers of two in [16, 1024], got " + std::to_string(rows) +
+        return fail(SHEAR_E_SIZE, "GPU path needs rows and cols powers of two in [16, 2048], got " + std::to_string(rows) +
                                       "x" + std::to_string(cols));
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);

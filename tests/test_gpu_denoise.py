@@ -233,7 +233,8 @@ def test_denoise_1024_columns(gpu):
     """The threshold row kernel at 1024 columns (8-row blocks whose two halves of a 16-row tile are
     regrouped onto one XCD, with a tail kept in order): a built 1024 x 1024 system (49 filters, one
     image) and a 32 x 1024 user bank (5 filters, 3 images: 60 blocks, 48 regrouped and a tail of
-    12), with gap thresholds, against the oracle; kept counts exact."""
+    12), with gap thresholds, against the oracle; kept counts exact. Also 2048 columns (a 16 x 2048
+    user bank)."""
     from paper_2006_04591_amd import ShearletSystem
 
     _say("case: denoise 1024x1024 K=49 B=1")
@@ -245,18 +246,19 @@ def test_denoise_1024_columns(gpu):
         torch.cuda.synchronize()
         assert np.array_equal(kept[0].cpu().numpy(), nw)
         assert _rel(y[0].cpu().numpy(), yw) <= TOL
-    _say("case: denoise 32x1024 user bank K=5 B=3")
-    rng = np.random.default_rng(1024)
-    ker = rng.standard_normal((5, 32, 1024))
-    ker = ker + ker[:, (-np.arange(32)) % 32][:, :, (-np.arange(1024)) % 1024]
-    S = np.fft.fft2(ker)
-    xb = (100.0 * rng.standard_normal((3, 32, 1024))).astype(np.float32)
-    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
-        rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
-        cases = [oracle_case(None, xb[b].astype(np.float64), 2.0 * 100.0 * rms, spectra=S) for b in range(3)]
-        thr = np.stack([c[0] for c in cases]).astype(np.float32)
-        y, kept = s.denoise(_to(xb, gpu), _to(thr, gpu), kept=True)
-        torch.cuda.synchronize()
-        for b in range(3):
-            assert np.array_equal(kept[b].cpu().numpy(), cases[b][2])
-            assert _rel(y[b].cpu().numpy(), cases[b][1]) <= TOL
+    for (N, M, K, B) in ((32, 1024, 5, 3), (16, 2048, 3, 2)):
+        _say(f"case: denoise {N}x{M} user bank K={K} B={B}")
+        rng = np.random.default_rng(M + K)
+        ker = rng.standard_normal((K, N, M))
+        ker = ker + ker[:, (-np.arange(N)) % N][:, :, (-np.arange(M)) % M]
+        S = np.fft.fft2(ker)
+        xb = (100.0 * rng.standard_normal((B, N, M))).astype(np.float32)
+        with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+            rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+            cases = [oracle_case(None, xb[b].astype(np.float64), 2.0 * 100.0 * rms, spectra=S) for b in range(B)]
+            thr = np.stack([c[0] for c in cases]).astype(np.float32)
+            y, kept = s.denoise(_to(xb, gpu), _to(thr, gpu), kept=True)
+            torch.cuda.synchronize()
+            for b in range(B):
+                assert np.array_equal(kept[b].cpu().numpy(), cases[b][2])
+                assert _rel(y[b].cpu().numpy(), cases[b][1]) <= TOL

@@ -250,3 +250,35 @@ def test_inpaint_uneven_sizes_match_oracle(gpu, n):
     for i in range(2):
         assert _rel(out[i].cpu().numpy(), wants[i]) <= TOL
     inp.close()
+
+
+def test_inpaint_2048_columns_user_bank(gpu):
+    """Algorithm 3 on 16 x 2048 images (the row kernel that mixes mask, masked image and estimate at
+    2048 columns) with a user filter bank, three iterations against the oracle with gap thresholds."""
+    from paper_2006_04591_amd import ShearletSystem
+
+    _say("case: inpaint 16x2048 user bank K=3 B=2, 3 iterations")
+    rng = np.random.default_rng(2048)
+    ker = rng.standard_normal((3, 16, 2048))
+    ker = ker + ker[:, (-np.arange(16)) % 16][:, :, (-np.arange(2048)) % 2048]
+    S = np.fft.fft2(ker)
+
+    class _Ref:
+        spectra = S
+        W = np.sum(np.abs(S) ** 2, axis=0)
+        rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+        K = 3
+
+    f = (100.0 + 50.0 * rng.standard_normal((2, 16, 2048))).astype(np.float32)
+    m = (rng.random((2, 16, 2048)) < 0.5).astype(np.float32)
+    fm = (f * m).astype(np.float32)
+    thr, want = [], []
+    for b in range(2):
+        rows, y = oracle_schedule(_Ref, fm[b], m[b], OA.delta_schedule(_d0(_Ref, fm[b]), 1.0, 3))
+        thr.append(rows)
+        want.append(y)
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        y = s.inpaint(_to(fm, gpu), _to(m, gpu), _to(np.stack(thr, axis=1), gpu))
+        torch.cuda.synchronize()
+        for b in range(2):
+            assert _rel(y[b].cpu().numpy(), want[b]) <= TOL

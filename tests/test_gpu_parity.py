@@ -135,11 +135,14 @@ def _random_bank(rng, K, N, M, real):
 
 @pytest.mark.parametrize("N,M,K,real,B", [(16, 16, 3, False, 1), (32, 64, 5, True, 3), (64, 16, 4, False, 2),
                                           (128, 32, 7, True, 5), (16, 1024, 2, False, 1), (1024, 16, 2, True, 1),
-                                          (32, 1024, 5, True, 3)])
+                                          (32, 1024, 5, True, 3), (2048, 2048, 2, True, 1), (2048, 32, 3, False, 2),
+                                          (16, 2048, 4, True, 3)])
 def test_user_bank_shapes(gpu, lib, N, M, K, real, B):
     """User filter banks of assorted shapes against the oracle. At 1024 columns the row passes run
     8-row blocks whose two halves of a 16-row tile are regrouped per 16 blocks: 32 x 1024 with 15
-    coefficient planes gives 60 blocks per pass (48 regrouped, a tail of 12 in order)."""
+    coefficient planes gives 60 blocks per pass (48 regrouped, a tail of 12 in order). 2048-point
+    columns are 128-thread FFT groups over two wavefronts (workgroup barriers between passes);
+    2048-point rows are 1024-point half-length FFTs of 16 points per thread."""
     from paper_2006_04591_amd import ShearletSystem
 
     rng = np.random.default_rng(N * 7 + M + K)
@@ -211,7 +214,7 @@ def test_errors(gpu, lib):
 
     _say("case: error paths")
     with pytest.raises(ShearError) as e:
-        ShearletSystem.build(2048, 2048, 4)
+        ShearletSystem.build(4096, 4096, 4)
     assert e.value.name == "SHEAR_E_SIZE"
     with pytest.raises(ShearError) as e:
         ShearletSystem.build(32, 32, 2)  # kernels do not fit
