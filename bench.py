@@ -484,7 +484,7 @@ def main() -> int:
                     help="images per chunk of the K-expanded intermediate (0 = whole batch)")
     ap.add_argument("--train-steps", type=int, default=1250, help="shrink: training steps (16 pairs each)")
     ap.add_argument("--schedule", default="",
-                    help="fwdinv/denoise/layer: fixed column-pass schedule 'pw_fwd,pw_inv,kg_fwd,kg_inv' instead of "
+                    help="fwdinv/denoise/layer: fixed column-pass schedule 'pw_fwd,pw_inv,kg_fwd,kg_inv[,pc_fwd,pc_inv]' instead of "
                          "the autotuner (counter runs use it so that one kernel variant runs)")
     ap.add_argument("--workload", default="fwdinv", choices=("fwdinv", "denoise", "layer", "inpaint", "shrink"),
                     help="fwdinv: shear_forward + shear_inverse (the headline); denoise: shear_denoise with the "
@@ -538,14 +538,14 @@ def main() -> int:
     shs.reserve(B)
     if args.schedule:
         schedule = tuple(int(v) for v in args.schedule.split(","))
-        if len(schedule) != 4:
-            print("bench.py: --schedule needs four integers pw_fwd,pw_inv,kg_fwd,kg_inv", file=sys.stderr)
+        if len(schedule) not in (4, 6):
+            print("bench.py: --schedule needs pw_fwd,pw_inv,kg_fwd,kg_inv[,pc_fwd,pc_inv]", file=sys.stderr)
             return 2
         shs.set_schedule(*schedule)
-        log(f"bench: fixed column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv): {schedule}")
+        log(f"bench: fixed column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv[, pc_fwd, pc_inv]): {schedule}")
     else:
         schedule = shs.autotune(B)
-        log(f"bench: autotuned column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv): {schedule}")
+        log(f"bench: autotuned column-pass schedule (pw_fwd, pw_inv, kg_fwd, kg_inv, pc_fwd, pc_inv): {schedule}")
     # denoising workload: hard threshold 3 sigma RMS_k on every plane (the listing of Section 4.2)
     thr = torch.from_numpy(np.tile(shs.paper_thresholds(SIGMA, factors=[3.0] * J), (B, 1))).to(dev)
     if layer:

@@ -217,6 +217,24 @@ int shear_inpaint_thresholds(const shear_system* s, const double* deltas, int it
 int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, float* f, int batch,
                   const float* thresholds, int iterations, void* hip_stream);
 
+/* Batched inpainting of images of several sizes (Section 4.3, Algorithm 3) in
+ * one graph launch: group g < n_groups runs shear_inpaint's iteration sequence
+ * with systems[g] (one system per image size) on its batch[g] images. The
+ * sequences of all groups are captured once per call shape as parallel
+ * branches of one HIP graph, held by systems[0] and re-captured when a
+ * system, its schedule or workspace, a pointer, a batch or the iteration count
+ * changes; each call replays it with one hipGraphLaunch on hip_stream. Arrays
+ * of n_groups entries: systems (distinct, built on the current device),
+ * f_masked, mask, f, batch (> 0) and thresholds (iterations*batch[g]*K_g
+ * float32 each, device), with the per-group meaning of shear_inpaint. With
+ * per-launch timing on in any system, the groups' launches are issued
+ * directly, one group after the other. SHEAR_E_INVALID for NULL arrays or
+ * entries, a system in two groups, batch[g] <= 0 or iterations < 1.
+ * Asynchronous. */
+int shear_inpaint_groups(shear_system* const* systems, int n_groups, const float* const* f_masked,
+                         const float* const* mask, float* const* f, const int* batch, const float* const* thresholds,
+                         int iterations, void* hip_stream);
+
 /* Learned shrinkage (not in the paper: a small network predicts the
  * thresholds of Section 4.2's hard thresholding per coefficient). With
  * z_k = c_k / (sigma_b RMS_k):
@@ -289,28 +307,37 @@ int shear_profile_enable(shear_system* s, int on);
  * previous read, and clears the record. */
 int shear_profile_read(shear_system* s, int* launches, double* total_ms);
 
-/* Column-pass schedule of the separate-launch kernels: pw_fwd / pw_inv
- * columns per block (16 or 8; 16 needs cols >= 32) and kg_fwd / kg_inv
- * filter groups (1..K: the K filters of a column panel are split over that
- * many blocks, so that small batches fill the device; the inverse then adds
- * the groups' partial sums in group order), in the forward and in the
- * inverse/adjoint column passes; 0 keeps the current value. The forward's
- * results do not depend on the schedule (every column and filter goes
- * through the same operations); the inverse's summation order over the
- * filters follows the groups, so it agrees to rounding. SHEAR_E_INVALID for
- * other values. Drops any captured inpainting graph. */
-int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv);
+/* Column-pass schedule of the separate-launch kernels:
+ *   pw_fwd / pw_inv: columns per block (16 or 8; 16 needs cols >= 32);
+ *   kg_fwd / kg_inv: filter groups (1..K: the K filters of a column panel are
+ *     split over that many blocks, so that small batches fill the device; the
+ *     inverse then adds the groups' partial sums in group order);
+ *   pc_fwd / pc_inv: points per thread of the rows-point column FFTs, i.e.
+ *     their radix sequence: the default (8 up to 512 points, 16 at 1024 and
+ *     2048) or, at 256 and 512 points, 16 (two radix-16 passes), at 1024
+ *     points, 8 (a 128-thread FFT group over two wavefronts; with 16-column
+ *     blocks, which would need 2048 threads, the default runs instead);
+ *     SHEAR_E_INVALID for any other value at that size;
+ * in the forward and in the inverse/adjoint column passes; 0 keeps the
+ * current value. The forward's results do not depend on the panel width or
+ * the filter split (every column and filter goes through the same
+ * operations); the points per thread and, in the inverse, the summation order
+ * over the filters change the rounding, so results agree to rounding.
+ * Drops any captured inpainting graph. */
+int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv, int pc_fwd, int pc_inv);
 
 /* Autotuner: times the column passes of both directions for every compiled
- * panel width and filter split in {1, 2, 4, 8} (at most K; the forward also
- * tries 16 and 32 when batch * cols/16 is below the device's compute units)
- * on the system's workspace at this batch size (clearing the workspace
- * first), five interleaved rounds keeping each candidate's fastest launch,
- * keeps the fastest of each direction (shear_set_schedule) and reports it
- * through the out-pointers (any may be NULL). Synchronous: waits for the device,
- * allocates the workspace for batch if needed, uses the null stream. Drops
- * any captured inpainting graph. */
-int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv);
+ * panel width, filter split in {1, 2, 4, 8} (at most K; the forward also tries
+ * 16 and 32 when batch * cols/16 is below the device's compute units) and
+ * points per thread (default and alternative, where there is one) on the
+ * system's workspace at this batch size (clearing the workspace first), five
+ * interleaved rounds keeping each candidate's fastest launch, keeps the
+ * fastest of each direction (shear_set_schedule) and reports it through the
+ * out-pointers (any may be NULL). Synchronous: waits for the device, allocates
+ * the workspace for batch if needed, uses the null stream. Drops any captured
+ * inpainting graph. */
+int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv, int* pc_fwd,
+                   int* pc_inv);
 
 /* Frees a system. The caller must have synchronised every stream that used it. */
 void shear_destroy_system(shear_system* s);

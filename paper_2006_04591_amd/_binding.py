@@ -39,6 +39,7 @@ EXPORTED = (
     "shear_denoise",
     "shear_denoise_thresholds",
     "shear_inpaint",
+    "shear_inpaint_groups",
     "shear_inpaint_thresholds",
     "shear_delta_schedule",
     "shear_profile_enable",
@@ -106,19 +107,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         getattr(lib, name).argtypes = [P, P, P, I, P]
     lib.shear_denoise.argtypes = [P, P, P, I, P, P, P]
     lib.shear_inpaint.argtypes = [P, P, P, P, I, P, I, P]
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.shear_inpaint_groups.argtypes = [PP, I, PP, PP, PP, pI, PP, I, P]
     lib.shear_denoise_thresholds.argtypes = [P, pD, I, pD, I, ctypes.POINTER(ctypes.c_float)]
     lib.shear_inpaint_thresholds.argtypes = [P, pD, I, I, ctypes.POINTER(ctypes.c_float)]
     lib.shear_delta_schedule.argtypes = [I, ctypes.c_double, ctypes.c_double, I, pD]
     for name in EXPORTED:
         if name not in ("shear_destroy_system", "shear_strerror", "shear_last_error"):
             getattr(lib, name).restype = I
-    lib.shear_set_schedule.argtypes = [P, I, I, I, I]
+    lib.shear_set_schedule.argtypes = [P, I, I, I, I, I, I]
     lib.shear_shrink_params_bytes.argtypes = [I, ctypes.POINTER(ctypes.c_size_t)]
     lib.shear_shrink_pack.argtypes = [P, P, P, P, P, P, P, P, P]
     lib.shear_shrink_apply.argtypes = [P, P, P, P, I, P, P, P]
     lib.shear_shrink_param_count.argtypes = [I]
     lib.shear_shrink_train_step.argtypes = [P, P, P, I, P, P, P, P, P, I, ctypes.c_float, ctypes.c_float, P, P]
-    lib.shear_autotune.argtypes = [P, I, pI, pI, pI, pI]
+    lib.shear_autotune.argtypes = [P, I, pI, pI, pI, pI, pI, pI]
     lib.shear_profile_enable.argtypes = [P, I]
     lib.shear_profile_read.argtypes = [P, pI, pD]
     lib.shear_destroy_system.argtypes = [P]
@@ -396,16 +399,17 @@ class ShearletSystem:
         return out
 
     # ------------------------------------------------------------ column-pass schedule
-    def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0, kg_fwd: int = 0, kg_inv: int = 0) -> None:
-        """Columns per block and filter groups of the forward and inverse column passes (shear_set_schedule);
-        0 keeps a value."""
-        _check(self._lib.shear_set_schedule(self._h, int(pw_fwd), int(pw_inv), int(kg_fwd), int(kg_inv)),
-               "shear_set_schedule")
+    def set_schedule(self, pw_fwd: int = 0, pw_inv: int = 0, kg_fwd: int = 0, kg_inv: int = 0, pc_fwd: int = 0,
+                     pc_inv: int = 0) -> None:
+        """Columns per block, filter groups and points per thread (radix sequence) of the forward and
+        inverse column passes (shear_set_schedule); 0 keeps a value."""
+        _check(self._lib.shear_set_schedule(self._h, int(pw_fwd), int(pw_inv), int(kg_fwd), int(kg_inv), int(pc_fwd),
+                                            int(pc_inv)), "shear_set_schedule")
 
     def autotune(self, batch: int):
         """Times the compiled column-pass schedules at this batch size and keeps the fastest
-        (shear_autotune); returns (pw_fwd, pw_inv, kg_fwd, kg_inv)."""
-        v = [ctypes.c_int() for _ in range(4)]
+        (shear_autotune); returns (pw_fwd, pw_inv, kg_fwd, kg_inv, pc_fwd, pc_inv)."""
+        v = [ctypes.c_int() for _ in range(6)]
         _check(self._lib.shear_autotune(self._h, int(batch), *[ctypes.byref(x) for x in v]), "shear_autotune")
         return tuple(x.value for x in v)
 

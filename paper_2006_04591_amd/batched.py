@@ -1,9 +1,9 @@
 """Batched inpainting of images of uneven sizes (Section 4.3, Algorithm 3).
 
-Images are grouped by size; each size has its own shearlet system, and each
-group runs as one shear_inpaint call (its whole iteration sequence captured
-as one HIP graph by the library) on a stream of its own, so the groups
-overlap on the GPU. Everything here is host-side grouping and marshalling.
+Images are grouped by size; each size has its own shearlet system, and one
+shear_inpaint_groups call runs every group: the library captures the groups'
+iteration sequences as parallel branches of one HIP graph and replays it with
+one launch. Everything here is host-side grouping and marshalling.
 """
 from __future__ import annotations
 
@@ -12,7 +12,9 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 import torch
 
-from ._binding import ShearletSystem
+import ctypes
+
+from ._binding import ShearletSystem, _check, _stream_ptr, load_library
 
 __all__ = ["UnevenInpainter", "default_scales"]
 
@@ -30,7 +32,6 @@ class UnevenInpainter:
         self._scales = scales
         self._autotune = autotune
         self._systems: Dict[Tuple[int, int], ShearletSystem] = {}
-        self._streams: Dict[Tuple[int, int], torch.cuda.Stream] = {}
         self._tuned: Dict[Tuple[int, int], int] = {}
         self.schedules: Dict[Tuple[int, int], Tuple[int, int]] = {}
 
@@ -54,38 +55,47 @@ class UnevenInpainter:
                 raise ValueError("images must be 2-D")
             groups.setdefault((int(t.shape[0]), int(t.shape[1])), []).append(i)
         result: List[Optional[torch.Tensor]] = [None] * n
-        cur = torch.cuda.current_stream()
-        pending = []
+        systems, fms, mks, outs, batches, thrs, iters = [], [], [], [], [], [], set()
         for key, ids in groups.items():
             s = self.system(*key)
             if self._autotune and self._tuned.get(key) != len(ids):
                 # the column-pass schedule of this size at this group's batch (synchronous)
                 self.schedules[key] = s.autotune(len(ids))
                 self._tuned[key] = len(ids)
-            st = self._streams.setdefault(key, torch.cuda.Stream())
-            st.wait_stream(cur)
-            with torch.cuda.stream(st):
-                fm = torch.stack([f_masked[i] for i in ids]).contiguous()
-                mk = torch.stack([masks[i] for i in ids]).contiguous()
-                sch = [np.asarray(schedules[i], dtype=np.float64) for i in ids]
+            fm = torch.stack([f_masked[i] for i in ids]).contiguous()
+            mk = torch.stack([masks[i] for i in ids]).contiguous()
+            sch = [np.asarray(schedules[i], dtype=np.float64) for i in ids]
+            if all(a.ndim == 1 for a in sch):
+                # scalar deltas per iteration and image, weighted per filter by the library
                 if len({a.shape[0] for a in sch}) != 1:
                     raise ValueError(f"images of size {key} need the same number of iterations")
-                if all(a.ndim == 1 for a in sch):
-                    # scalar deltas per iteration and image, weighted per filter by the library
-                    thr = s.inpaint_thresholds(np.stack(sch, axis=1), len(ids))
-                elif all(a.ndim == 2 and a.shape[1] == s.K for a in sch):
-                    thr = np.ascontiguousarray(np.stack(sch, axis=1), dtype=np.float32)
-                else:
-                    raise ValueError(f"schedules of size {key} must all be (iterations,) or all (iterations, {s.K})")
-                thr_t = torch.from_numpy(thr).to(fm.device)
-                y = s.inpaint(fm, mk, thr_t, stream=st)
-                for j, i in enumerate(ids):
-                    result[i] = y[j]
-                for t in (fm, mk, thr_t, y):
-                    t.record_stream(st)
-            pending.append(st)
-        for st in pending:
-            cur.wait_stream(st)
+                thr = s.inpaint_thresholds(np.stack(sch, axis=1), len(ids))
+            elif all(a.ndim == 2 and a.shape[1] == s.K for a in sch):
+                if len({a.shape[0] for a in sch}) != 1:
+                    raise ValueError(f"images of size {key} need the same number of iterations")
+                thr = np.ascontiguousarray(np.stack(sch, axis=1), dtype=np.float32)
+            else:
+                raise ValueError(f"schedules of size {key} must all be (iterations,) or all (iterations, {s.K})")
+            iters.add(thr.shape[0])
+            y = torch.empty_like(fm)
+            systems.append(s)
+            fms.append(fm)
+            mks.append(mk)
+            outs.append(y)
+            batches.append(len(ids))
+            thrs.append(torch.from_numpy(thr).to(fm.device))
+            for j, i in enumerate(ids):
+                result[i] = y[j]
+        if len(iters) != 1:
+            raise ValueError("every image needs the same number of iterations")
+        G = len(systems)
+        VP = ctypes.c_void_p * G
+        _check(load_library().shear_inpaint_groups(
+            VP(*[s._h for s in systems]), G, VP(*[t.data_ptr() for t in fms]), VP(*[t.data_ptr() for t in mks]),
+            VP(*[t.data_ptr() for t in outs]), (ctypes.c_int * G)(*batches), VP(*[t.data_ptr() for t in thrs]),
+            int(iters.pop()), _stream_ptr(None)), "shear_inpaint_groups")
+        # the graph reads these buffers when it runs: keep them alive until the next call
+        self._keep = (fms, mks, outs, thrs)
         return result  # type: ignore[return-value]
 
     def close(self) -> None:

@@ -19,7 +19,14 @@ struct DevPlan {
     int pw_inv = 16;
     int kg_fwd = 1;           // filter groups of the column passes (blocks per panel; capped at K)
     int kg_inv = 1;
+    int pc_fwd = 0;           // points per thread of the column FFTs (0: col_points_default(N); else
+    int pc_inv = 0;           // col_points_alternative(N), a different radix sequence)
 };
+
+// Points per thread of the N-point column FFTs: the default, and the alternative the column-pass
+// schedule may select instead (0 if there is none for this N).
+int col_points_default(int N);
+int col_points_alternative(int N);
 
 // Partial-sum scratch of the inverse column pass for nimg images (float2 elements; 0 when kg_inv is 1).
 inline size_t cols_inv_part_elems(const DevPlan& d, int nimg) {

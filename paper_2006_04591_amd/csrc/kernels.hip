@@ -507,9 +507,9 @@ __global__ __launch_bounds__(ROWS*(M / 2) / Pts<M / 2>::value) void k_rows_thres
                                           kept ? kept + plane : nullptr, (int)threadIdx.x);
 }
 
-template <int N, int PW>
+template <int N, int PW, int PP = ColPts<N>::value>
 struct ColCfg {
-    static constexpr int P = ColPts<N>::value;
+    static constexpr int P = PP;
     static constexpr int T = N / P;
     static constexpr int THREADS = PW * T;
     static constexpr size_t LDS = ((size_t)PW * ColScratch<N, P>::value + N) * sizeof(float2);
@@ -519,13 +519,13 @@ struct ColCfg {
 // consecutive filters (block index = pan + npan (g + kg b)), so that small batches still
 // fill the device. The forward recomputes the panel's column FFT in each group; the
 // inverse writes one partial sum per group and k_cols_inv_finish adds them in group order.
-template <int N, int PW, bool REAL>
-__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const float2* __restrict__ A,
+template <int N, int PW, bool REAL, int PP>
+__global__ __launch_bounds__((ColCfg<N, PW, PP>::THREADS)) void k_cols_fwd(const float2* __restrict__ A,
                                                                     float2* __restrict__ Tout,
                                                                     const void* __restrict__ filt, int L, int K,
                                                                     int npan, int kper, int kg,
                                                                     const float2* __restrict__ twN, float scale) {
-    constexpr int P = ColCfg<N, PW>::P;
+    constexpr int P = ColCfg<N, PW, PP>::P;
     extern __shared__ float2 lds[];
     const int pan = blockIdx.x % npan, g = (blockIdx.x / npan) % kg, b = blockIdx.x / (npan * kg);
     float2 xh[P];
@@ -538,15 +538,15 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_fwd(const flo
 
 // kg == 1: V[b] = colIFFT(sum_k ...); kg > 1: part[b][g] (L x N column-major) and, for packed
 // column 0, part0[b][g] (N) receive the group's sums.
-template <int N, int PW, bool REAL>
-__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const float2* __restrict__ U,
+template <int N, int PW, bool REAL, int PP>
+__global__ __launch_bounds__((ColCfg<N, PW, PP>::THREADS)) void k_cols_inv(const float2* __restrict__ U,
                                                                     float2* __restrict__ V,
                                                                     const void* __restrict__ filt, int L, int K,
                                                                     int npan, int kper, int kg,
                                                                     float2* __restrict__ part,
                                                                     float2* __restrict__ part0,
                                                                     const float2* __restrict__ twN) {
-    constexpr int P = ColCfg<N, PW>::P, T = N / P;
+    constexpr int P = ColCfg<N, PW, PP>::P, T = N / P;
     extern __shared__ float2 lds[];
     const int pan = blockIdx.x % npan, g = (blockIdx.x / npan) % kg, b = blockIdx.x / (npan * kg);
     const int tid = (int)threadIdx.x;
@@ -575,12 +575,12 @@ __global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv(const flo
 }
 
 // V[b] panel = colIFFT(sum_g part[b][g] [+ conj of the mirrored column-0 partials]), g in order
-template <int N, int PW>
-__global__ __launch_bounds__((ColCfg<N, PW>::THREADS)) void k_cols_inv_finish(const float2* __restrict__ part,
+template <int N, int PW, int PP>
+__global__ __launch_bounds__((ColCfg<N, PW, PP>::THREADS)) void k_cols_inv_finish(const float2* __restrict__ part,
                                                                            const float2* __restrict__ part0,
                                                                            float2* __restrict__ V, int L, int npan,
                                                                            int kg, const float2* __restrict__ twN) {
-    constexpr int P = ColCfg<N, PW>::P, T = N / P;
+    constexpr int P = ColCfg<N, PW, PP>::P, T = N / P;
     extern __shared__ float2 lds[];
     const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
     const int tid = (int)threadIdx.x;
@@ -692,32 +692,32 @@ inline void kgroups(int K, int kg_req, int& kper, int& kg) {
     kg = (K + kper - 1) / kper;
 }
 
-template <int N, int PW>
+template <int N, int PW, int PP>
 hipError_t cols_fwd_t(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
                       hipStream_t st) {
-    using C = ColCfg<N, PW>;
+    using C = ColCfg<N, PW, PP>;
     const int npan = d.L / PW;
     int kper, kg;
     kgroups(d.K, d.kg_fwd, kper, kg);
     const size_t blocks = (size_t)npan * kg * nimg;
     if (d.real) {
-        hipError_t e = set_lds(k_cols_fwd<N, PW, true>, C::LDS);
+        hipError_t e = set_lds(k_cols_fwd<N, PW, true, PP>, C::LDS);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cols_fwd<N, PW, true>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, A, T,
+        hipLaunchKernelGGL((k_cols_fwd<N, PW, true, PP>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, A, T,
                            filt, d.L, d.K, npan, kper, kg, d.twN, scale);
     } else {
-        hipError_t e = set_lds(k_cols_fwd<N, PW, false>, C::LDS);
+        hipError_t e = set_lds(k_cols_fwd<N, PW, false, PP>, C::LDS);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cols_fwd<N, PW, false>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, A, T,
+        hipLaunchKernelGGL((k_cols_fwd<N, PW, false, PP>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, A, T,
                            filt, d.L, d.K, npan, kper, kg, d.twN, scale);
     }
     return hipGetLastError();
 }
 
-template <int N, int PW>
+template <int N, int PW, int PP>
 hipError_t cols_inv_t(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
                       hipStream_t st) {
-    using C = ColCfg<N, PW>;
+    using C = ColCfg<N, PW, PP>;
     const int npan = d.L / PW;
     int kper, kg;
     kgroups(d.K, d.kg_inv, kper, kg);
@@ -725,26 +725,79 @@ hipError_t cols_inv_t(const DevPlan& d, const float2* U, float2* V, int nimg, co
     float2* part0 = kg > 1 ? part + (size_t)nimg * kg * d.L * d.N : nullptr;
     const size_t blocks = (size_t)npan * kg * nimg;
     if (d.real) {
-        hipError_t e = set_lds(k_cols_inv<N, PW, true>, C::LDS);
+        hipError_t e = set_lds(k_cols_inv<N, PW, true, PP>, C::LDS);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cols_inv<N, PW, true>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, U, V,
+        hipLaunchKernelGGL((k_cols_inv<N, PW, true, PP>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, U, V,
                            filt, d.L, d.K, npan, kper, kg, part, part0, d.twN);
     } else {
-        hipError_t e = set_lds(k_cols_inv<N, PW, false>, C::LDS);
+        hipError_t e = set_lds(k_cols_inv<N, PW, false, PP>, C::LDS);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_cols_inv<N, PW, false>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, U, V,
+        hipLaunchKernelGGL((k_cols_inv<N, PW, false, PP>), dim3((unsigned)blocks), dim3(C::THREADS), C::LDS, st, U, V,
                            filt, d.L, d.K, npan, kper, kg, part, part0, d.twN);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || kg == 1) return e;
-    e = set_lds(k_cols_inv_finish<N, PW>, C::LDS);
+    e = set_lds(k_cols_inv_finish<N, PW, PP>, C::LDS);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_cols_inv_finish<N, PW>), dim3((unsigned)((size_t)npan * nimg)), dim3(C::THREADS), C::LDS, st,
+    hipLaunchKernelGGL((k_cols_inv_finish<N, PW, PP>), dim3((unsigned)((size_t)npan * nimg)), dim3(C::THREADS), C::LDS, st,
                        part, part0, V, d.L, npan, kg, d.twN);
     return hipGetLastError();
 }
 
+// The alternative points per thread of an N-point column FFT (a different radix sequence), 0 where
+// there is none: 16 at 256 and 512 points (two passes of 16 instead of 8 x 8 x 8 or 8 x 8 x 4),
+// 8 at 1024 (8 x 8 x 8 x 2, a 128-thread group over two wavefronts with workgroup barriers).
+template <int N>
+constexpr int alt_col_pts() {
+    return (N == 256 || N == 512) ? 16 : (N == 1024 ? 8 : 0);
+}
+
+// The column pass at the plan's points per thread: pc == the alternative (when the block stays
+// within 1024 threads) or the default ColPts<N>.
+template <int N, int PW>
+hipError_t cols_fwd_pc(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
+                       hipStream_t st) {
+    constexpr int ALT = alt_col_pts<N>();
+    if constexpr (ALT > 0 && PW * (N / ALT) <= 1024) {
+        if (d.pc_fwd == ALT) return cols_fwd_t<N, PW, ALT>(d, A, T, nimg, filt, scale, st);
+    }
+    return cols_fwd_t<N, PW, ColPts<N>::value>(d, A, T, nimg, filt, scale, st);
+}
+
+template <int N, int PW>
+hipError_t cols_inv_pc(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
+                       hipStream_t st) {
+    constexpr int ALT = alt_col_pts<N>();
+    if constexpr (ALT > 0 && PW * (N / ALT) <= 1024) {
+        if (d.pc_inv == ALT) return cols_inv_t<N, PW, ALT>(d, U, V, nimg, filt, part, st);
+    }
+    return cols_inv_t<N, PW, ColPts<N>::value>(d, U, V, nimg, filt, part, st);
+}
+
 }  // namespace
+
+int col_points_alternative(int N) {
+    switch (N) {
+        case 256: return alt_col_pts<256>();
+        case 512: return alt_col_pts<512>();
+        case 1024: return alt_col_pts<1024>();
+    }
+    return 0;
+}
+
+int col_points_default(int N) {
+    switch (N) {
+        case 16: return ColPts<16>::value;
+        case 32: return ColPts<32>::value;
+        case 64: return ColPts<64>::value;
+        case 128: return ColPts<128>::value;
+        case 256: return ColPts<256>::value;
+        case 512: return ColPts<512>::value;
+        case 1024: return ColPts<1024>::value;
+        case 2048: return ColPts<2048>::value;
+    }
+    return 0;
+}
 
 bool size_supported(int n) {
     return n == 16 || n == 32 || n == 64 || n == 128 || n == 256 || n == 512 || n == 1024 || n == 2048;
@@ -851,12 +904,12 @@ hipError_t launch_rows_thresh(const DevPlan& d, float2* planes, int nplanes, con
 
 hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nimg, const void* filt, float scale,
                            hipStream_t st) {
-    SHEAR_COLS_SWITCH(d.pw_fwd, 4, cols_fwd_t, d, A, T, nimg, filt, scale, st)
+    SHEAR_COLS_SWITCH(d.pw_fwd, 4, cols_fwd_pc, d, A, T, nimg, filt, scale, st)
 }
 
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
                            hipStream_t st) {
-    SHEAR_COLS_SWITCH(d.pw_inv, 8, cols_inv_t, d, U, V, nimg, filt, part, st)
+    SHEAR_COLS_SWITCH(d.pw_inv, 8, cols_inv_pc, d, U, V, nimg, filt, part, st)
 }
 
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {

@@ -52,6 +52,10 @@ struct shear_system {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<const void*> graph_key;
+    // shear_inpaint_groups led by this system: the branches of every group in one graph
+    hipGraph_t ggraph = nullptr;
+    hipGraphExec_t ggexec = nullptr;
+    std::vector<const void*> ggraph_key;
     // learned shrinkage: scales and hidden activations
     void* ws2 = nullptr;
     size_t ws2_bytes = 0;
@@ -227,6 +231,8 @@ void release(shear_system* s) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
+    if (s->ggexec) (void)hipGraphExecDestroy(s->ggexec);
+    if (s->ggraph) (void)hipGraphDestroy(s->ggraph);
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
@@ -811,7 +817,112 @@ int shear_inpaint(shear_system* s, const float* f_masked, const float* mask, flo
     return SHEAR_OK;
 }
 
-int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv) {
+namespace {
+
+void drop_group_graph(shear_system* s) {
+    if (s->ggexec) (void)hipGraphExecDestroy(s->ggexec);
+    if (s->ggraph) (void)hipGraphDestroy(s->ggraph);
+    s->ggexec = nullptr;
+    s->ggraph = nullptr;
+    s->ggraph_key.clear();
+}
+
+// What a captured group sequence depends on, per group: the system, its filter bank, workspace and
+// schedule, and the call's pointers and batch.
+void group_key(shear_system* const* sys, int n, const float* const* fm, const float* const* mask, float* const* f,
+               const int* batch, const float* const* thr, int iterations, const int* chunk,
+               std::vector<const void*>& key) {
+    auto v = [](long long x) { return (const void*)(intptr_t)x; };
+    key.assign({v(n), v(iterations)});
+    for (int g = 0; g < n; ++g) {
+        const shear_system* s = sys[g];
+        const shear::DevPlan& d = s->plan;
+        key.insert(key.end(), {(const void*)s, s->dev_block, s->ws, v((long long)s->ws_bytes), v(s->rows), v(s->cols),
+                               v(s->K), v(d.pw_fwd), v(d.pw_inv), v(d.kg_fwd), v(d.kg_inv), v(d.pc_fwd), v(d.pc_inv),
+                               fm[g], mask[g], f[g], thr[g], v(batch[g]), v(chunk[g])});
+    }
+}
+
+}  // namespace
+
+int shear_inpaint_groups(shear_system* const* systems, int n_groups, const float* const* f_masked,
+                         const float* const* mask, float* const* f, const int* batch, const float* const* thresholds,
+                         int iterations, void* stream) {
+    if (!systems || n_groups < 1 || !f_masked || !mask || !f || !batch || !thresholds)
+        return fail(SHEAR_E_INVALID, "NULL array or no group");
+    if (iterations < 1) return fail(SHEAR_E_INVALID, "iterations must be positive");
+    std::vector<int> chunk((size_t)n_groups, 0);
+    for (int g = 0; g < n_groups; ++g) {
+        for (int h = 0; h < g; ++h)
+            if (systems[h] == systems[g]) return fail(SHEAR_E_INVALID, "a system appears in two groups");
+        int rc = check_call(systems[g], f_masked[g], f[g], batch[g]);
+        if (rc != SHEAR_OK) return rc;
+        if (!mask[g] || !thresholds[g]) return fail(SHEAR_E_INVALID, "mask or thresholds pointer is NULL");
+        if ((rc = prepare_ws(systems[g], batch[g], chunk[(size_t)g])) != SHEAR_OK) return rc;
+    }
+    shear_system* lead = systems[0];
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    bool prof = false;
+    for (int g = 0; g < n_groups; ++g) prof = prof || systems[g]->prof_on;
+    if (prof) {
+        // per-launch timing needs the launches themselves: the groups one after another
+        for (int g = 0; g < n_groups; ++g) {
+            e = enqueue_inpaint(systems[g], f_masked[g], mask[g], f[g], batch[g], thresholds[g], iterations,
+                                chunk[(size_t)g], st);
+            if (e != hipSuccess) return hip_fail(e, "inpainting launch");
+        }
+        return SHEAR_OK;
+    }
+    std::vector<const void*> key;
+    group_key(systems, n_groups, f_masked, mask, f, batch, thresholds, iterations, chunk.data(), key);
+    if (!lead->ggexec || key != lead->ggraph_key) {
+        drop_group_graph(lead);
+        for (int g = 0; g < n_groups; ++g)
+            if (!systems[g]->cap_stream &&
+                (e = hipStreamCreateWithFlags(&systems[g]->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreateWithFlags");
+        std::vector<hipEvent_t> ev((size_t)n_groups, nullptr);  // [0] forks, [g > 0] joins
+        for (auto& x : ev)
+            if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) {
+                for (auto y : ev)
+                    if (y) (void)hipEventDestroy(y);
+                return hip_fail(e, "hipEventCreate");
+            }
+        hipStream_t origin = lead->cap_stream;
+        hipError_t el = hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed);
+        if (el == hipSuccess) el = hipEventRecord(ev[0], origin);
+        // group 0 on the origin stream, every other group on a branch forked from it and joined back
+        for (int g = 1; g < n_groups && el == hipSuccess; ++g) {
+            hipStream_t bs = systems[g]->cap_stream;
+            if ((el = hipStreamWaitEvent(bs, ev[0], 0)) != hipSuccess) break;
+            if ((el = enqueue_inpaint(systems[g], f_masked[g], mask[g], f[g], batch[g], thresholds[g], iterations,
+                                      chunk[(size_t)g], bs)) != hipSuccess)
+                break;
+            if ((el = hipEventRecord(ev[(size_t)g], bs)) != hipSuccess) break;
+        }
+        if (el == hipSuccess)
+            el = enqueue_inpaint(lead, f_masked[0], mask[0], f[0], batch[0], thresholds[0], iterations, chunk[0], origin);
+        for (int g = 1; g < n_groups && el == hipSuccess; ++g) el = hipStreamWaitEvent(origin, ev[(size_t)g], 0);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(origin, &graph);
+        for (auto y : ev) (void)hipEventDestroy(y);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return hip_fail(el != hipSuccess ? el : e, "capturing the grouped inpainting sequence");
+        }
+        lead->ggraph = graph;
+        if ((e = hipGraphInstantiate(&lead->ggexec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+            drop_group_graph(lead);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        lead->ggraph_key = key;
+    }
+    if ((e = hipGraphLaunch(lead->ggexec, st)) != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return SHEAR_OK;
+}
+
+int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv, int pc_fwd, int pc_inv) {
     if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
     const int L = s->cols / 2;
     for (int pw : {pw_fwd, pw_inv}) {
@@ -820,19 +931,31 @@ int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int 
     }
     for (int kg : {kg_fwd, kg_inv})
         if (kg < 0 || kg > s->K) return fail(SHEAR_E_INVALID, "filter groups must be in [0, K]");
+    const int pdef = shear::col_points_default(s->rows), palt = shear::col_points_alternative(s->rows);
+    for (int pc : {pc_fwd, pc_inv})
+        if (pc != 0 && pc != pdef && pc != palt)
+            return fail(SHEAR_E_INVALID, "points per thread of the " + std::to_string(s->rows) + "-point column FFTs must be 0, " +
+                                             std::to_string(pdef) + (palt ? " or " + std::to_string(palt) : std::string()));
     if (pw_fwd) s->plan.pw_fwd = pw_fwd;
     if (pw_inv) s->plan.pw_inv = pw_inv;
     if (kg_fwd) s->plan.kg_fwd = kg_fwd;
     if (kg_inv) s->plan.kg_inv = kg_inv;
+    if (pc_fwd) s->plan.pc_fwd = pc_fwd;
+    if (pc_inv) s->plan.pc_inv = pc_inv;
     drop_graph(s);  // a captured inpainting sequence holds the old schedule and workspace layout
     return SHEAR_OK;
 }
 
-int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv) {
+int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv, int* pc_fwd,
+                   int* pc_inv) {
     int rc = check_call(s, s, s, batch);
     if (rc != SHEAR_OK) return rc;
     std::vector<int> pws = {8};
     if (s->cols / 2 >= 16) pws.insert(pws.begin(), 16);
+    // points per thread of the column FFTs (the radix sequence): the default, and the alternative where
+    // there is one
+    std::vector<int> pcs = {shear::col_points_default(s->rows)};
+    if (shear::col_points_alternative(s->rows)) pcs.push_back(shear::col_points_alternative(s->rows));
     // filter splits: up to 8 groups in the inverse (each group adds a partial-sum plane per image);
     // the forward, which needs no partial sums, also tries 16 and 32 when the batch's panels alone
     // (at 8 columns) would leave the device's compute units idle
@@ -870,15 +993,20 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
     // drifts of the device's clocks and interference hit every candidate alike
     constexpr int kRounds = 5;
     for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
-        std::vector<std::pair<int, int>> cand;
+        struct Cand {
+            int pw, kg, pc;
+        };
+        std::vector<Cand> cand;
         for (int pw : pws)
-            for (int kg : (dir == 0 ? kgs_fwd : kgs)) cand.emplace_back(pw, kg);
+            for (int kg : (dir == 0 ? kgs_fwd : kgs))
+                for (int pc : pcs) cand.push_back({pw, kg, pc});
         std::vector<float> best(cand.size(), -1.0f);
         for (int round = 0; round <= kRounds && e == hipSuccess; ++round) {  // round 0 warms up
             for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
                 shear::DevPlan d = s->plan;
-                (dir == 0 ? d.pw_fwd : d.pw_inv) = cand[ci].first;
-                (dir == 0 ? d.kg_fwd : d.kg_inv) = cand[ci].second;
+                (dir == 0 ? d.pw_fwd : d.pw_inv) = cand[ci].pw;
+                (dir == 0 ? d.kg_fwd : d.kg_inv) = cand[ci].kg;
+                (dir == 0 ? d.pc_fwd : d.pc_inv) = cand[ci].pc;
                 if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) break;
                 e = dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
                              : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, part, nullptr);
@@ -889,17 +1017,17 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
                 if (round > 0 && (best[ci] < 0.0f || ms < best[ci])) best[ci] = ms;
             }
         }
-        int pick_pw = pws[0], pick_kg = 1;
+        Cand pick_c{pws[0], 1, pcs[0]};
         float pick = -1.0f;
         for (size_t ci = 0; ci < cand.size(); ++ci)
             if (best[ci] >= 0.0f && (pick < 0.0f || best[ci] < pick)) {
                 pick = best[ci];
-                pick_pw = cand[ci].first;
-                pick_kg = cand[ci].second;
+                pick_c = cand[ci];
             }
         if (e == hipSuccess) {
-            (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick_pw;
-            (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = pick_kg;
+            (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick_c.pw;
+            (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = pick_c.kg;
+            (dir == 0 ? s->plan.pc_fwd : s->plan.pc_inv) = pick_c.pc;
         }
     }
     (void)hipEventDestroy(e0);
@@ -909,6 +1037,8 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
     if (pw_inv) *pw_inv = s->plan.pw_inv;
     if (kg_fwd) *kg_fwd = s->plan.kg_fwd;
     if (kg_inv) *kg_inv = s->plan.kg_inv;
+    if (pc_fwd) *pc_fwd = s->plan.pc_fwd ? s->plan.pc_fwd : shear::col_points_default(s->rows);
+    if (pc_inv) *pc_inv = s->plan.pc_inv ? s->plan.pc_inv : shear::col_points_default(s->rows);
     return SHEAR_OK;
 }
 

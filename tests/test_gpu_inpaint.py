@@ -134,6 +134,49 @@ def test_inpaint_graph_replays_match_direct_launches(sys128, gpu):
     assert torch.equal(out, direct2) and not torch.equal(direct, direct2)
 
 
+def test_grouped_graph_replays_match_direct_launches(gpu):
+    """shear_inpaint_groups: the groups of three sizes in one captured graph (one branch per size),
+    replayed several times with eager work and synchronisations in between; every replay equals the
+    directly launched sequences (per-launch timing switches capture off) and each size's own
+    shear_inpaint call."""
+    from paper_2006_04591_amd import UnevenInpainter
+
+    _say("case: grouped inpainting graph (128x128 / 256x256 / 128x256) replays vs direct launches")
+    inp = UnevenInpainter(scales=lambda r, c: 2 if max(r, c) <= 128 else 3, autotune=False)
+    sizes = [(128, 128), (256, 256), (128, 256), (256, 256), (128, 128)]
+    fms, ms, scheds = [], [], []
+    for i, (r, c) in enumerate(sizes):
+        f = synth.cartoon(r, c, seed=5600 + i)
+        m = synth.random_mask(r, c, 0.5, seed=5650 + i)
+        fms.append(_to(f * m, gpu))
+        ms.append(_to(m, gpu))
+        scheds.append(OA.delta_schedule(300.0, 2.0, 4))
+    for s in (inp.system(128, 128), inp.system(256, 256), inp.system(128, 256)):
+        s.profile(True)
+    direct = [t.clone() for t in inp.run(fms, ms, scheds)]
+    torch.cuda.synchronize()
+    for s in inp._systems.values():
+        s.profile_read()
+        s.profile(False)
+    for rep in range(3):
+        out = inp.run(fms, ms, scheds)
+        junk = torch.randn((1 << 20,), device=gpu).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for i in range(len(sizes)):
+            assert torch.equal(out[i], direct[i]), (rep, i)
+    # each size group alone through shear_inpaint gives the same images
+    for key in ((128, 128), (256, 256), (128, 256)):
+        ids = [i for i, sz in enumerate(sizes) if sz == key]
+        s = inp.system(*key)
+        thr = _to(s.inpaint_thresholds(scheds[ids[0]], len(ids)), gpu)
+        y = s.inpaint(torch.stack([fms[i] for i in ids]), torch.stack([ms[i] for i in ids]), thr)
+        torch.cuda.synchronize()
+        for j, i in enumerate(ids):
+            assert torch.equal(y[j], direct[i]), key
+    inp.close()
+
+
 def test_inpaint_linear_schedule_keeps_known_pixels(sys128, gpu):
     s, ref = sys128
     _say("case: inpaint linear decay to zero")

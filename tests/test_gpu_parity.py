@@ -449,45 +449,65 @@ def test_config4_256_k33_b32_sampled(gpu, lib):
 
 @pytest.mark.parametrize("N,M,J,B", [(256, 256, 3, 4), (1024, 1024, 4, 2), (512, 128, 2, 3), (512, 512, 4, 1)])
 def test_schedules_agree_and_autotune(gpu, lib, N, M, J, B):
-    """Every column-pass schedule (panel width, filter groups) transforms each column and filter with the
-    same operations: the forward is bitwise identical; the inverse sums the filters group by group, so it
-    agrees to rounding; the autotuner keeps one of them."""
+    """Every column-pass schedule transforms each column and filter with the same operations at given
+    points per thread: across panel widths and filter groups the forward is bitwise identical; the
+    inverse sums the filters group by group, so it agrees to rounding. The other points per thread (a
+    different radix sequence: 16 at 256 and 512 points, 8 at 1024) agree to rounding and with the
+    oracle. The autotuner keeps one of them."""
     from paper_2006_04591_amd import ShearletSystem
 
     _say(f"case: schedules {N}x{M} J={J} B={B}")
     ref = OF.build_system(N, M, J)
+    alt = {256: 16, 512: 16, 1024: 8}[N]
+    dflt = {256: 8, 512: 8, 1024: 16}[N]
     with ShearletSystem.build(N, M, J) as s:
         xh = synth.cartoon_batch(B, N, M, config=8, sigma=5.0)
         x = _to(xh, gpu)
         res = {}
-        for pw in (16, 8):
-            for kg in (1, 3, 8, 16):
-                s.set_schedule(pw, pw, kg, kg)
-                c = s.forward(x)
-                res[(pw, kg)] = (c, s.inverse(c), s.adjoint(c))
+        for pc in (dflt, alt):
+            for pw in (16, 8):
+                for kg in (1, 3, 8, 16):
+                    s.set_schedule(pw, pw, kg, kg, pc, pc)
+                    c = s.forward(x)
+                    res[(pc, pw, kg)] = (c, s.inverse(c), s.adjoint(c))
         torch.cuda.synchronize()
-        c0, y0, a0 = res[(16, 1)]
+        c0, y0, a0 = res[(dflt, 16, 1)]
+
+        def eff(pc, pw):  # at 1024 points the alternative needs 8-column blocks (16 x 128 threads is too many)
+            return dflt if (N == 1024 and pw == 16) else pc
+
+        ref_alt = res[(alt, 8, 1)][0]
         for key, (c, y, a) in res.items():
-            assert torch.equal(c, c0), key
+            if eff(key[0], key[1]) == dflt:
+                assert torch.equal(c, c0), key
+            else:
+                assert torch.equal(c, ref_alt), key
+                assert _rel(c.cpu().numpy(), c0.cpu().numpy()) <= 1e-6, key
             assert _rel(y.cpu().numpy(), y0.cpu().numpy()) <= 1e-6, key
             assert _rel(a.cpu().numpy(), a0.cpu().numpy()) <= 1e-6, key
-        # the split inverse against the oracle (one image)
-        yk = res[(8, 8)][1][0].double().cpu().numpy()
-        c_in = res[(8, 8)][0][0].double().cpu().numpy()
-        assert _rel(yk, OT.inverse_plain(c_in, ref.spectra, ref.W)) <= TOL
+        # the split inverse and the alternative radix sequence against the oracle (one image)
+        for key in ((dflt, 8, 8), (alt, 8, 8), (alt, 8, 1)):
+            yk = res[key][1][0].double().cpu().numpy()
+            c_in = res[key][0][0].double().cpu().numpy()
+            assert _rel(yk, OT.inverse_plain(c_in, ref.spectra, ref.W)) <= TOL, key
+            assert _rel(c_in, OT.forward_plain(xh[0].astype(np.float64), ref.spectra)) <= TOL, key
         assert _rel(y0.cpu().numpy(), xh) <= TOL
-        pf, pi, kf, ki = s.autotune(B)
+        pf, pi, kf, ki, qf, qi = s.autotune(B)
         # the forward may split up to 32 ways at small batches, the inverse up to 8
         assert pf in (8, 16) and pi in (8, 16) and kf in (1, 2, 4, 8, 16, 32) and kf <= ref.K and ki in (1, 2, 4, 8)
+        assert qf in (dflt, alt) and qi in (dflt, alt)
         c = s.forward(x)
         y = s.inverse(c)
         torch.cuda.synchronize()
-        assert torch.equal(c, c0)
+        assert torch.equal(c, c0 if eff(qf, pf) == dflt else ref_alt)
         assert _rel(y.cpu().numpy(), y0.cpu().numpy()) <= 1e-6
         with pytest.raises(Exception):
             s.set_schedule(12, 0)
         with pytest.raises(Exception):
             s.set_schedule(0, 0, ref.K + 1, 0)
+        with pytest.raises(Exception):
+            s.set_schedule(0, 0, 0, 0, 4, 0)  # no 4-point-per-thread column FFTs
+        s.set_schedule(0, 0, 0, 0, dflt, dflt)
 
 
 def test_schedule_narrow_columns(gpu, lib):
