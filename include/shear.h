@@ -326,16 +326,21 @@ int shear_profile_read(shear_system* s, int* launches, double* total_ms);
  * Drops any captured inpainting graph. */
 int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv, int pc_fwd, int pc_inv);
 
-/* Autotuner: times the column passes of both directions for every compiled
- * panel width, filter split in {1, 2, 4, 8} (at most K; the forward also tries
- * 16 and 32 when batch * cols/16 is below the device's compute units) and
- * points per thread (default and alternative, where there is one) on the
- * system's workspace at this batch size (clearing the workspace first), five
- * interleaved rounds keeping each candidate's fastest launch, keeps the
- * fastest of each direction (shear_set_schedule) and reports it through the
- * out-pointers (any may be NULL). Synchronous: waits for the device, allocates
- * the workspace for batch if needed, uses the null stream. Drops any captured
- * inpainting graph. */
+/* Autotuner: chooses the column-pass schedule of each direction among every
+ * compiled panel width, filter split in {1, 2, 4, 8} (at most K; the forward
+ * also tries 16 and 32 when batch * cols/16 is below the device's compute
+ * units) and points per thread (default and alternative, where there is one).
+ * Each candidate is timed inside whole shear_forward + shear_inverse steps at
+ * this batch size (the forward's candidates with the current inverse schedule,
+ * then the inverse's with the chosen forward), on temporary images and
+ * coefficients it allocates for the call (batch * (2 + K) * rows * cols
+ * floats) and frees before it returns; five interleaved rounds, each
+ * candidate keeps the median of its step times. Keeps the fastest of each
+ * direction (shear_set_schedule) and reports it through the out-pointers (any
+ * may be NULL). Synchronous: waits for the device, allocates the workspace for
+ * batch if needed, uses the null stream; per-launch timing is paused during the
+ * call. SHEAR_E_NOMEM if the temporary buffers cannot be allocated. Drops any
+ * captured inpainting graph. */
 int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg_fwd, int* kg_inv, int* pc_fwd,
                    int* pc_inv);
 

@@ -31,6 +31,8 @@ __all__ = [
     "forward_plain",
     "inverse_plain",
     "adjoint_plain",
+    "forward_plain_threaded",
+    "inverse_plain_threaded",
     "correlate_direct",
 ]
 
@@ -102,6 +104,23 @@ def inverse_plain(coeffs: np.ndarray, spectra: np.ndarray, W: np.ndarray) -> np.
 def adjoint_plain(coeffs: np.ndarray, spectra: np.ndarray) -> np.ndarray:
     """Shift-free adjoint: y = Re ifft2( sum_k fft2(c_k) Psi_k )."""
     return np.real(np.fft.ifft2(np.sum(np.fft.fft2(np.asarray(coeffs, dtype=np.float64)) * spectra, axis=0)))
+
+
+def forward_plain_threaded(x: np.ndarray, spectra: np.ndarray, workers: int) -> np.ndarray:
+    """forward_plain with scipy.fft's multi-threaded FFTs (the K planes' transforms split over
+    `workers` threads); same definition, different FFT library and summation order."""
+    import scipy.fft as sf
+
+    X = sf.fft2(np.asarray(x, dtype=np.float64), workers=workers)
+    return np.real(sf.ifft2(X[None] * np.conj(spectra), workers=workers))
+
+
+def inverse_plain_threaded(coeffs: np.ndarray, spectra: np.ndarray, W: np.ndarray, workers: int) -> np.ndarray:
+    """inverse_plain with scipy.fft's multi-threaded FFTs over `workers` threads."""
+    import scipy.fft as sf
+
+    S = np.sum(sf.fft2(np.asarray(coeffs, dtype=np.float64), workers=workers) * spectra, axis=0)
+    return np.real(sf.ifft2(S / W, workers=workers))
 
 
 def correlate_direct(x: np.ndarray, kernel: np.ndarray) -> np.ndarray:

@@ -335,7 +335,9 @@ hipError_t take_event(shear_system* s, hipEvent_t& e) {
         s->ev_free.pop_back();
         return hipSuccess;
     }
-    return hipEventCreate(&e);
+    // timing-only events: no system-scope fence (cache write-back and invalidate) when recorded, so
+    // that bracketing a launch does not slow the launches around it
+    return hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
 }
 
 // Runs one launch; with profiling on, brackets it with two events on the same stream.
@@ -976,23 +978,36 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
     drop_graph(s);  // a captured inpainting sequence holds the old schedule
     hipError_t e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
-    // defined contents for the timing runs
-    e = shear::launch_zero_u32((unsigned*)s->ws, (int)std::min<size_t>(s->ws_bytes / 4, (size_t)1 << 30), nullptr);
-    if (e != hipSuccess) return hip_fail(e, "workspace clear");
-    const size_t pb = plane_bytes(s) / sizeof(float2);
-    float2* A = (float2*)s->ws;
-    float2* T = A + (size_t)batch * pb;
-    float2* part = T + (size_t)chunk * s->K * pb;
-    const float scale = (float)(1.0 / ((double)s->rows * s->cols));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
-        if (e0) (void)hipEventDestroy(e0);
-        return hip_fail(e, "hipEventCreate");
+    // Candidates are timed inside whole forward + inverse steps on temporary images and coefficients:
+    // a column pass's time depends on what the launches around it leave in the caches (at 16 x
+    // 512 x 512 x 49 a forward split of 8 measured 0.165-0.18 ms between the inverse's passes against
+    // 0.14 ms unsplit, while alone the two were within 3 %).
+    const size_t img = (size_t)s->rows * s->cols;
+    float* xt = nullptr;
+    float* ct = nullptr;
+    if ((e = hipMalloc(&xt, 2 * (size_t)batch * img * sizeof(float))) != hipSuccess)
+        return fail(SHEAR_E_NOMEM, std::string("autotune: image buffers: ") + hipGetErrorString(e));
+    if ((e = hipMalloc(&ct, (size_t)batch * s->K * img * sizeof(float))) != hipSuccess) {
+        (void)hipFree(xt);
+        return fail(SHEAR_E_NOMEM, std::string("autotune: coefficient buffer: ") + hipGetErrorString(e));
     }
-    // each candidate is timed once per round, rounds interleaved, and keeps its fastest launch:
-    // drifts of the device's clocks and interference hit every candidate alike
+    float* yt = xt + (size_t)batch * img;
+    // defined, non-zero images: each a copy of the first N x M values of the forward filter table
+    // (which holds K N (M/2 + 1) values, at least N x M from K = 2 on), else zeros
+    const size_t filt_vals = (size_t)s->K * (s->cols / 2 + 1) * s->rows * (s->plan.real ? 1 : 2);
+    e = shear::launch_zero_u32((unsigned*)xt, (int)std::min<size_t>(2 * (size_t)batch * img, (size_t)1 << 30), nullptr);
+    for (int b = 0; b < batch && e == hipSuccess && filt_vals >= img; ++b)
+        e = hipMemcpyAsync(xt + (size_t)b * img, s->filt_fwd, img * sizeof(float), hipMemcpyDeviceToDevice, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess && (e = hipEventCreateWithFlags(&e0, hipEventDisableSystemFence)) == hipSuccess)
+        e = hipEventCreateWithFlags(&e1, hipEventDisableSystemFence);
+    const bool prof = s->prof_on;
+    s->prof_on = false;  // the steps' launches are not part of the per-launch record
+    int call_rc = SHEAR_OK;
+    // each candidate is timed once per round, rounds interleaved (drifts of the device's clocks and
+    // interference hit every candidate alike), and keeps the median of its rounds
     constexpr int kRounds = 5;
-    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+    for (int dir = 0; dir < 2 && e == hipSuccess && call_rc == SHEAR_OK; ++dir) {
         struct Cand {
             int pw, kg, pc;
         };
@@ -1000,39 +1015,51 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
         for (int pw : pws)
             for (int kg : (dir == 0 ? kgs_fwd : kgs))
                 for (int pc : pcs) cand.push_back({pw, kg, pc});
-        std::vector<float> best(cand.size(), -1.0f);
-        for (int round = 0; round <= kRounds && e == hipSuccess; ++round) {  // round 0 warms up
-            for (size_t ci = 0; ci < cand.size() && e == hipSuccess; ++ci) {
-                shear::DevPlan d = s->plan;
-                (dir == 0 ? d.pw_fwd : d.pw_inv) = cand[ci].pw;
-                (dir == 0 ? d.kg_fwd : d.kg_inv) = cand[ci].kg;
-                (dir == 0 ? d.pc_fwd : d.pc_inv) = cand[ci].pc;
-                if ((e = hipEventRecord(e0, nullptr)) != hipSuccess) break;
-                e = dir == 0 ? shear::launch_cols_fwd(d, A, T, chunk, s->filt_fwd, scale, nullptr)
-                             : shear::launch_cols_inv(d, T, A, chunk, s->filt_inv, part, nullptr);
-                if (e != hipSuccess) break;
-                if ((e = hipEventRecord(e1, nullptr)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) break;
+        std::vector<std::vector<float>> times(cand.size());
+        for (int round = 0; round <= kRounds && e == hipSuccess && call_rc == SHEAR_OK; ++round) {  // round 0 warms up
+            for (size_t ci = 0; ci < cand.size() && e == hipSuccess && call_rc == SHEAR_OK; ++ci) {
+                const shear::DevPlan keep = s->plan;
+                (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = cand[ci].pw;
+                (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = cand[ci].kg;
+                (dir == 0 ? s->plan.pc_fwd : s->plan.pc_inv) = cand[ci].pc;
+                if ((e = hipEventRecord(e0, nullptr)) == hipSuccess &&
+                    (call_rc = shear_forward(s, xt, ct, batch, nullptr)) == SHEAR_OK &&
+                    (call_rc = shear_inverse(s, ct, yt, batch, nullptr)) == SHEAR_OK &&
+                    (e = hipEventRecord(e1, nullptr)) == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                s->plan = keep;
                 float ms = 0.0f;
-                if ((e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) break;
-                if (round > 0 && (best[ci] < 0.0f || ms < best[ci])) best[ci] = ms;
+                if (e == hipSuccess && call_rc == SHEAR_OK && (e = hipEventElapsedTime(&ms, e0, e1)) == hipSuccess &&
+                    round > 0)
+                    times[ci].push_back(ms);
             }
         }
-        Cand pick_c{pws[0], 1, pcs[0]};
+        if (e != hipSuccess || call_rc != SHEAR_OK) break;
+        size_t pick_i = 0;
         float pick = -1.0f;
-        for (size_t ci = 0; ci < cand.size(); ++ci)
-            if (best[ci] >= 0.0f && (pick < 0.0f || best[ci] < pick)) {
-                pick = best[ci];
-                pick_c = cand[ci];
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+            std::vector<float> t = times[ci];
+            if (t.empty()) continue;
+            std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
+            const float med = t[t.size() / 2];
+            if (pick < 0.0f || med < pick) {
+                pick = med;
+                pick_i = ci;
             }
-        if (e == hipSuccess) {
-            (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = pick_c.pw;
-            (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = pick_c.kg;
-            (dir == 0 ? s->plan.pc_fwd : s->plan.pc_inv) = pick_c.pc;
         }
+        (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = cand[pick_i].pw;
+        (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = cand[pick_i].kg;
+        (dir == 0 ? s->plan.pc_fwd : s->plan.pc_inv) = cand[pick_i].pc;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    s->prof_on = prof;
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    hipError_t es = hipDeviceSynchronize();
+    (void)hipFree(ct);
+    (void)hipFree(xt);
+    if (call_rc != SHEAR_OK) return call_rc;
     if (e != hipSuccess) return hip_fail(e, "autotune launch");
+    if (es != hipSuccess) return hip_fail(es, "hipDeviceSynchronize after autotune");
     if (pw_fwd) *pw_fwd = s->plan.pw_fwd;
     if (pw_inv) *pw_inv = s->plan.pw_inv;
     if (kg_fwd) *kg_fwd = s->plan.kg_fwd;

@@ -43,7 +43,7 @@ def _counter_csv(path, rows):
             w.writerow(r)
 
 
-def test_traffic_summary_calibrates_and_keys_by_source(tmp_path):
+def test_counter_summary_calibrates_and_keys_by_source(tmp_path):
     cal = 1 << 29
     kern = "void shear::(anonymous namespace)::k_rows_c2r<512, 1, 16>(HIP_vector_type<float, 2u> const*, float*)"
     # the copy kernel's FETCH_SIZE reads half its bytes, WRITE_SIZE all of them (KiB, summed over the
@@ -60,18 +60,33 @@ def test_traffic_summary_calibrates_and_keys_by_source(tmp_path):
     _counter_csv(tmp_path / "write.csv", [
         {"Dispatch_Id": 5, "Kernel_Name": kern, "Counter_Name": "WRITE_SIZE", "Counter_Value": 3000.0},
         {"Dispatch_Id": 9, "Kernel_Name": kern, "Counter_Name": "WRITE_SIZE", "Counter_Value": 3200.0}])
+    # VALU instructions: plain counts summed over the counter's instances, averaged over dispatches
+    _counter_csv(tmp_path / "valu.csv", [
+        {"Dispatch_Id": 5, "Kernel_Name": kern, "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 4.0e7},
+        {"Dispatch_Id": 5, "Kernel_Name": kern, "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 4.0e7},
+        {"Dispatch_Id": 9, "Kernel_Name": kern, "Counter_Name": "SQ_INSTS_VALU", "Counter_Value": 9.0e7}])
     src = tmp_path / "kernels.hip"
     src.write_text("// one version of the kernels\n")
-    out = tmp_path / "traffic.json"
+    out = tmp_path / "counters.json"
     assert bench.traffic_summary(str(tmp_path / "fetch.csv"), str(tmp_path / "write.csv"), str(tmp_path / "calf.csv"),
-                                 str(tmp_path / "calw.csv"), cal, out_path=str(out), src=str(src)) == 0
+                                 str(tmp_path / "calw.csv"), cal, out_path=str(out), src=str(src),
+                                 valu_csv=str(tmp_path / "valu.csv")) == 0
     rec = json.loads(out.read_text())
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
     ent = rec["kernels"]["rows_c2r_coeffs"]
     assert ent["fetch_bytes"] == pytest.approx(2.0 * 1024 * (1500.0 + 1700.0) / 2)  # mean over dispatches, x 2
     assert ent["write_bytes"] == pytest.approx(1024 * (3000.0 + 3200.0) / 2)
+    assert ent["valu_wave_instructions"] == pytest.approx(8.5e7)
     got = bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src))
     assert got == pytest.approx(ent["fetch_bytes"] + ent["write_bytes"])
+    # VALU side: 8.5e7 wave instructions at 256 CUs x 2.4 GHz x 1 per clock take 0.1383 ms
+    v = bench.valu_bound("rows_c2r_coeffs", 0.2766, path=str(out), src=str(src))
+    assert v["min_ms"] == pytest.approx(8.5e7 / 614.4e9 * 1e3) and v["frac"] == pytest.approx(0.5, rel=1e-3)
+    # counters taken on one workload say nothing about another (a 256x256 layer, say)
+    assert bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src),
+                                       workload="32x256x256x33") is None
+    assert bench.valu_bound("rows_c2r_coeffs", 0.2766, path=str(out), src=str(src), workload="32x256x256x33") is None
     # a changed kernel source makes the stored counters stale
     src.write_text("// another version of the kernels\n")
     assert bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src)) is None
+    assert bench.valu_bound("rows_c2r_coeffs", 0.2766, path=str(out), src=str(src)) is None

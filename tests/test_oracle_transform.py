@@ -208,3 +208,15 @@ def test_coefficients_real_for_hermitian_bank(cfg1):
     X = T.fourier(x)
     z = T.inverse_fourier(X[None] * np.conj(s.centred))
     assert np.max(np.abs(z.imag)) <= 1e-13 * np.max(np.abs(z.real))
+
+
+def test_threaded_forms_match_plain(cfg1):
+    """The multi-threaded scipy.fft forms (the all-cores host baseline) compute the plain forms."""
+    s, x = cfg1
+    c = T.forward_plain(x, s.spectra)
+    ct = T.forward_plain_threaded(x, s.spectra, workers=4)
+    assert np.linalg.norm(ct - c) <= 1e-12 * np.linalg.norm(c)
+    y = T.inverse_plain(c, s.spectra, s.W)
+    yt = T.inverse_plain_threaded(c, s.spectra, s.W, workers=4)
+    assert np.linalg.norm(yt - y) <= 1e-12 * np.linalg.norm(y)
+    assert np.linalg.norm(yt - x) <= 1e-10 * np.linalg.norm(x)
