@@ -74,7 +74,7 @@ template <int CINP, int OUTC, int MODE, bool COEF_IN = false>
 constexpr size_t conv_lds_bytes() {
     constexpr size_t in = (size_t)HH * HW * Pix<staged_ch<CINP, COEF_IN>()>::value * 2,
                      out = (size_t)TH * TW * OUTC * 2;
-    return (MODE == 2 || in >= out) ? in : out;
+    return (MODE == 2 || MODE == 5 || in >= out) ? in : out;
 }
 
 __device__ __forceinline__ float sigmoidf(float x) { return 1.0f / (1.0f + expf(-x)); }
@@ -111,69 +111,91 @@ __device__ __forceinline__ void stage(const ConvArgs& a, unsigned short* s, int 
     }
 }
 
+// Four bfloat16 of 4 floats, rounded to nearest even (v_cvt_pk_bf16_f32), as one 8-byte word.
+__device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 lo = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const bf16x2 hi = __builtin_convertvector((f32x2){c, d}, bf16x2);
+    return make_uint2(__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi));
+}
+
 // Stages the halo tile of one image straight from the FP32 channel-first coefficient planes:
 // z = bf16(c x scale[b][k]) channel-last, zero beyond the a.cin real channels (the values
-// k_pack_z would write). The TW interior pixels of a tile row are read as aligned 16-byte
-// vectors, the two halo columns one value each. The halo loads come first, then the interior in
-// batches of up to 32 channels; as in stage, a batch's loads are all issued before its first
-// LDS store.
+// k_pack_z would write). Work unit: 8 consecutive channels (one 16-byte run of a staged pixel) of
+// 4 consecutive interior pixels of one tile row: 8 aligned 16-byte loads, one per channel plane,
+// become 4 16-byte LDS stores. Lanes take the channel groups fastest: in each load instruction
+// the 8 lanes of one group read the 8 16-byte pieces of one 128-byte row segment of a plane, and
+// in each store the lanes of one pixel write its runs as contiguous bytes. A lane always has the same channel
+// group (256 threads, a multiple of the group count), so it loads its 8 scales once. The two halo
+// columns go the same way with one value per channel. All of a thread's loads are issued before
+// its first LDS store.
 template <int CS>
 __device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0, int cb) {
-    constexpr int PIX = Pix<CS>::value, QW = TW / 4;
-    constexpr int SB = CS < 32 ? CS : 32;  // channels per batch of loads (registers)
-    static_assert(CS % SB == 0, "whole batches");
-    constexpr int TOTAL = SB * HH * QW, NIT = (TOTAL + THREADS - 1) / THREADS;
-    constexpr int HTOTAL = CS * HH * 2, HNIT = (HTOTAL + THREADS - 1) / THREADS;
+    constexpr int PIX = Pix<CS>::value, QW = TW / 4, G = CS / 8;
+    static_assert(CS % 8 == 0 && THREADS % G == 0, "whole channel groups, one per lane");
+    constexpr int TOTAL = G * QW * HH, NIT = (TOTAL + THREADS - 1) / THREADS;
+    constexpr int HTOTAL = G * HH * 2, HNIT = (HTOTAL + THREADS - 1) / THREADS;
     const int N = a.N, M = a.M, K = a.cin;
-    float h[HNIT], hs[HNIT];
+    const int g = (int)threadIdx.x % G;
+    const size_t plane = (size_t)N * M;
+    const int k0 = cb + 8 * g;
+    const float* base = a.coef + ((size_t)b * K + k0) * plane;
+    float sc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) sc[c] = (k0 + c < K) ? a.scale[b * K + k0 + c] : 0.0f;
+    float h[HNIT][8];
 #pragma unroll
     for (int j = 0; j < HNIT; ++j) {
         const int i = (int)threadIdx.x + j * THREADS;
-        const int side = i % 2, yy = (i / 2) % HH, kl = i / (2 * HH), k = cb + kl;
-        const int xx = side ? HW - 1 : 0;
-        h[j] = hs[j] = 0.0f;
-        if (i < HTOTAL && k < K) {
-            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-            h[j] = a.coef[(((size_t)b * K + k) * N + y) * M + x];
-            hs[j] = a.scale[b * K + k];
+        const int side = (i / G) % 2, yy = i / (2 * G);
+        const int y = (y0 + yy - 1 + N) & (N - 1), x = side ? (x0 + TW) & (M - 1) : (x0 - 1 + M) & (M - 1);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) h[j][c] = (i < HTOTAL && k0 + c < K) ? base[c * plane + (size_t)y * M + x] : 0.0f;
+    }
+    float4 v[NIT][8];
+#pragma unroll
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
+        const int q = (i / G) % QW, yy = i / (G * QW);
+        const int y = (y0 + yy - 1 + N) & (N - 1);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            v[j][c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (i < TOTAL && k0 + c < K)
+                v[j][c] = *reinterpret_cast<const float4*>(base + c * plane + (size_t)y * M + x0 + 4 * q);
         }
     }
-#pragma unroll 1
-    for (int sb = 0; sb < CS; sb += SB) {
-        float4 v[NIT];
-        float sc[NIT];
 #pragma unroll
-        for (int j = 0; j < NIT; ++j) {
-            const int i = (int)threadIdx.x + j * THREADS;
-            const int q = i % QW, yy = (i / QW) % HH, kl = sb + i / (QW * HH), k = cb + kl;
-            v[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            sc[j] = 0.0f;
-            if (i < TOTAL && k < K) {
-                const int y = (y0 + yy - 1 + N) & (N - 1);
-                v[j] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * K + k) * N + y) * M + x0 + 4 * q);
-                sc[j] = a.scale[b * K + k];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NIT; ++j) {
-            const int i = (int)threadIdx.x + j * THREADS;
-            if (i < TOTAL) {
-                const int q = i % QW, yy = (i / QW) % HH, kl = sb + i / (QW * HH);
-                unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + kl;
-                d[0] = f2bf(v[j].x * sc[j]);
-                d[PIX] = f2bf(v[j].y * sc[j]);
-                d[2 * PIX] = f2bf(v[j].z * sc[j]);
-                d[3 * PIX] = f2bf(v[j].w * sc[j]);
-            }
+    for (int j = 0; j < NIT; ++j) {
+        const int i = (int)threadIdx.x + j * THREADS;
+        if (i < TOTAL) {
+            const int q = (i / G) % QW, yy = i / (G * QW);
+            unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + 8 * g;
+            const float4* w = v[j];
+            const uint2 p0a = pack_bf16x4(w[0].x * sc[0], w[1].x * sc[1], w[2].x * sc[2], w[3].x * sc[3]);
+            const uint2 p0b = pack_bf16x4(w[4].x * sc[4], w[5].x * sc[5], w[6].x * sc[6], w[7].x * sc[7]);
+            const uint2 p1a = pack_bf16x4(w[0].y * sc[0], w[1].y * sc[1], w[2].y * sc[2], w[3].y * sc[3]);
+            const uint2 p1b = pack_bf16x4(w[4].y * sc[4], w[5].y * sc[5], w[6].y * sc[6], w[7].y * sc[7]);
+            const uint2 p2a = pack_bf16x4(w[0].z * sc[0], w[1].z * sc[1], w[2].z * sc[2], w[3].z * sc[3]);
+            const uint2 p2b = pack_bf16x4(w[4].z * sc[4], w[5].z * sc[5], w[6].z * sc[6], w[7].z * sc[7]);
+            const uint2 p3a = pack_bf16x4(w[0].w * sc[0], w[1].w * sc[1], w[2].w * sc[2], w[3].w * sc[3]);
+            const uint2 p3b = pack_bf16x4(w[4].w * sc[4], w[5].w * sc[5], w[6].w * sc[6], w[7].w * sc[7]);
+            *reinterpret_cast<uint4*>(d) = make_uint4(p0a.x, p0a.y, p0b.x, p0b.y);
+            *reinterpret_cast<uint4*>(d + PIX) = make_uint4(p1a.x, p1a.y, p1b.x, p1b.y);
+            *reinterpret_cast<uint4*>(d + 2 * PIX) = make_uint4(p2a.x, p2a.y, p2b.x, p2b.y);
+            *reinterpret_cast<uint4*>(d + 3 * PIX) = make_uint4(p3a.x, p3a.y, p3b.x, p3b.y);
         }
     }
 #pragma unroll
     for (int j = 0; j < HNIT; ++j) {
         const int i = (int)threadIdx.x + j * THREADS;
         if (i < HTOTAL) {
-            const int side = i % 2, yy = (i / 2) % HH, kl = i / (2 * HH);
-            const int xx = side ? HW - 1 : 0;
-            s[(yy * HW + xx) * PIX + kl] = f2bf(h[j] * hs[j]);
+            const int side = (i / G) % 2, yy = i / (2 * G);
+            const float* w = h[j];
+            const uint2 pa = pack_bf16x4(w[0] * sc[0], w[1] * sc[1], w[2] * sc[2], w[3] * sc[3]);
+            const uint2 pb = pack_bf16x4(w[4] * sc[4], w[5] * sc[5], w[6] * sc[6], w[7] * sc[7]);
+            *reinterpret_cast<uint4*>(s + (yy * HW + (side ? HW - 1 : 0)) * PIX + 8 * g) = make_uint4(pa.x, pa.y, pb.x, pb.y);
         }
     }
 }
@@ -221,33 +243,15 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lk = 8 * (l / 16);
     const unsigned short* W = a.W;
-    // steps (tap, 32-channel chunk kc) in order. PIPE: the weight fragments of the next step are
-    // loaded before the current step's products, so that their latency overlaps them (NT x 4 more
-    // VGPRs; the shrink epilogue's kernel loses a wave per SIMD to them and runs slower)
+    // steps (tap, 32-channel chunk kc) in order
     constexpr int KCN = CS / 32, STEPS = 9 * KCN;
     auto wfrag = [&](int it, int nt) {
         const int tap = it / KCN, kc = it % KCN;
         return *reinterpret_cast<const bf16x8*>(W + ((size_t)(co0 + nt * 16 + lr) * 9 + tap) * CINP + cb + kc * 32 +
                                                 lk);
     };
-    bf16x8 bfr[NT];
-    if constexpr (PIPE) {
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) bfr[nt] = wfrag(0, nt);
-    }
-#pragma unroll 1
-    for (int it = 0; it < STEPS; ++it) {
+    auto step = [&](int it, const bf16x8(&bf)[NT]) {
         const int tap = it / KCN, kc = it % KCN, dy = tap / 3, dx = tap % 3;
-        const int nx = (it + 1 < STEPS) ? it + 1 : it;  // the last step re-loads its own fragments
-        bf16x8 bnx[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            if constexpr (PIPE) {
-                bnx[nt] = wfrag(nx, nt);
-            } else {
-                bfr[nt] = wfrag(it, nt);
-            }
-        }
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int row = 2 * w + mt / 2, xs = (mt % 2) * 16;
@@ -255,32 +259,81 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
                 *reinterpret_cast<const bf16x8*>(s + ((row + dy) * HW + xs + lr + dx) * PIX + kc * 32 + lk);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bfr[nt], acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bf[nt], acc[mt][nt], 0, 0, 0);
         }
-        if constexpr (PIPE) {
+    };
+    if constexpr (PIPE) {
+        // fully unrolled; the weight fragments are loaded PD steps ahead of their products, so that
+        // their latency (an L2 hit, several times one step's products) overlaps PD steps of products
+        // ((PD + 1) x NT x 4 VGPRs). A scheduling barrier after each step's loads keeps them there:
+        // with a distance of one step and no barrier, the scheduler moved each load down to its use
+        // and every step waited for L2.
+        constexpr int PD = 2;
+        bf16x8 bq[STEPS][NT];
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) bfr[nt] = bnx[nt];
+        for (int it = 0; it < PD && it < STEPS; ++it)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) bq[it][nt] = wfrag(it, nt);
+#pragma unroll
+        for (int it = 0; it < STEPS; ++it) {
+            if (it + PD < STEPS) {
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) bq[it + PD][nt] = wfrag(it + PD, nt);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            step(it, bq[it]);
+        }
+    } else {
+        // one step at a time (the shrink epilogue's kernel keeps its registers for waves)
+#pragma unroll 1
+        for (int it = 0; it < STEPS; ++it) {
+            bf16x8 bf[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) bf[nt] = wfrag(it, nt);
+            step(it, bf);
         }
     }
 }
 
+// Tile of a conv block. Hardware blocks go to the 8 XCDs in turn (block w on XCD w mod 8), each XCD
+// with its own L2. Each XCD takes a contiguous range of the tile order (x fastest, then rows, then
+// images), so that horizontally and vertically adjacent tiles, whose halos are each other's
+// interiors, run on one XCD close in time and the halo re-reads hit its L2 (a tile's two halo
+// columns of the channel-first coefficient planes are 4 bytes of a 128-byte line each: fetched
+// from memory per tile, they tripled the first layer's traffic). A tail of fewer than 8 blocks
+// keeps its order.
+__device__ __forceinline__ int conv_tile() {
+    const int w = (int)blockIdx.x, per = (int)gridDim.x / 8;
+    if (w >= per * 8) return w;
+    return (w % 8) * per + w / 8;
+}
+
 // MODE 1: bf16 activations (or the packed z) -> relu -> bf16 activations;
-// MODE 2: activations -> o + b -> tau = softplus -> shrink of the coefficients;
+// MODE 2: activations -> o + b -> shrink of the coefficients where |c scale| >= tau = softplus(o);
+// MODE 5: MODE 2 that also writes tau;
 // MODE 3 (training, last layer): o -> smooth-gate loss (summed into *loss) and its gradient d o, stored as
 //   bf16 channel-last planes [b][y][x][OUTC] (zero beyond K and on the low-pass plane);
 // MODE 4 (training, backward data): gradient planes -> conv with flipped, transposed weights, times the relu
 //   mask of the saved activation (mask_act > 0) -> bf16 gradient activations.
 // COEF_IN: the input is staged from the coefficients (stage_coef) instead of a.in.
+// Waves per SIMD a conv kernel's registers must allow, where its LDS allows them: the layer staged
+// from the coefficients holds 3 blocks per CU by its LDS (49 KB at 64 channels), the hidden layer 5
+// (27 KB); the prefetched weight fragments would otherwise cost each a wave.
+template <int CINP, int MODE, bool COEF_IN>
+constexpr int conv_min_waves() {
+    return COEF_IN ? 3 : ((MODE == 1 && CINP == 32) ? 5 : 1);
+}
+
 template <int CINP, int COUTP, int MODE, int OUTC = 32, bool COEF_IN = false>
-__global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
+__global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE, COEF_IN>())) void k_conv3x3(ConvArgs a) {
     constexpr int NT = COUTP / 16;
     extern __shared__ unsigned short smem[];
     unsigned short* s_in = smem;
-    const int tx = a.M / TW, ty = a.N / TH;
-    const int bx = blockIdx.x % tx, by = (blockIdx.x / tx) % ty, b = blockIdx.x / (tx * ty);
+    const int tx = a.M / TW, ty = a.N / TH, tile = conv_tile();
+    const int bx = tile % tx, by = (tile / tx) % ty, b = tile / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
     constexpr int CS = staged_ch<CINP, COEF_IN>();
-    static_assert(MODE != 2 || CS == CINP, "the shrink layer stages its whole input once");
+    static_assert((MODE != 2 && MODE != 5) || CS == CINP, "the shrink layer stages its whole input once");
     auto stage_part = [&](int cb) {
         if constexpr (COEF_IN) {
             stage_coef<CS>(a, s_in, b, y0, x0, cb);
@@ -288,20 +341,32 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
             stage<CINP, CS>(a, s_in, b, y0, x0, cb);
         }
     };
-    if constexpr (MODE == 2) {
+    constexpr bool SHRINK = (MODE == 2 || MODE == 5);
+    if constexpr (SHRINK) {
         stage_part(0);
         __syncthreads();
     }
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lm = 4 * (l / 16);
-    if constexpr (MODE == 2) {
+    if constexpr (SHRINK) {
         // o = acc + bias, tau = softplus(o) (0 on the low-pass plane), keep |c scale| >= tau. A lane
         // holds 4 consecutive pixels of one channel, so it reads and writes the channel-first
         // coefficient planes directly as 16-byte vectors. At most 32 output channels per pass over
         // the staged tile, so that fewer accumulators leave room for more waves per SIMD.
         // (48 padded channels go in three passes of 16: a pass never reads weight rows past COUTP)
+        // MODE 5 writes tau and decides with it. MODE 2 (no tau output) decides without forming
+        // tau: with a = |c scale| >= 0, m = max(o, 0), u = e^-|o| in (0, 1] and d = a - m,
+        // softplus(o) = m + log1p(u), so a >= softplus(o) <=> d >= 0 and expm1(d) >= u. Every d
+        // >= 0.75 passes (expm1(0.75) > 1 >= u); below, expm1 is its Taylor polynomial of degree 9
+        // (remainder < 2e-8 relative). One hardware exponential replaces the exponential, logarithm
+        // and reciprocal of softplus, and the decision keeps softplus's relative precision for small
+        // and large thresholds alike.
         constexpr int CG = COUTP <= 32 ? COUTP : (COUTP % 32 == 0 ? 32 : 16), NG = CG / 16;
         static_assert(COUTP % CG == 0, "the passes cover the padded output channels exactly");
+        constexpr float L2E = 1.44269504088896341f;
+        // offset of the lane's first vector in a plane: row y0 + 2 w, column x0 + lm; vector mt is
+        // (mt / 2) rows and (mt % 2) 16 columns further
+        const size_t pix0 = (size_t)(y0 + 2 * w) * a.M + x0 + lm;
 #pragma unroll 1
         for (int c0 = 0; c0 < COUTP; c0 += CG) {
         // the pass's coefficient vectors, bias and scale are loaded before its products, so that
@@ -309,20 +374,21 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         // each load would also wait for those stores: one memory counter covers both)
         float4 cvs[NG][4];
         float biass[NG], scs[NG];
+        size_t offs[NG];
 #pragma unroll
         for (int nt = 0; nt < NG; ++nt) {
             const int k = c0 + nt * 16 + lr;
             biass[nt] = scs[nt] = 0.0f;
+            offs[nt] = ((size_t)b * a.cout + k) * a.N * a.M + pix0;
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) cvs[nt][mt] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             if (k < a.cout) {
                 biass[nt] = a.bias[k];
                 scs[nt] = a.scale[b * a.cout + k];
+                const float* cp = a.coef + offs[nt];
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
-                    cvs[nt][mt] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * a.cout + k) * a.N + y) * a.M + x);
-                }
+                for (int mt = 0; mt < 4; ++mt)
+                    cvs[nt][mt] = *reinterpret_cast<const float4*>(cp + (mt / 2) * a.M + (mt % 2) * 16);
             }
         }
         f32x4 acc[4][NG];
@@ -332,23 +398,42 @@ __global__ __launch_bounds__(THREADS) void k_conv3x3(ConvArgs a) {
         for (int nt = 0; nt < NG; ++nt) {
             const int k = c0 + nt * 16 + lr;
             if (k >= a.cout) continue;
+            const bool lowpass = (k == a.lowpass);
             const float bias = biass[nt];
             const float sc = scs[nt];
-            const bool lowpass = (k == a.lowpass);
+            float* op = a.out_f + offs[nt];
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const int y = y0 + 2 * w + mt / 2, x = x0 + (mt % 2) * 16 + lm;
-                const size_t off = (((size_t)b * a.cout + k) * a.N + y) * a.M + x;
+                const int vo = (mt / 2) * a.M + (mt % 2) * 16;
                 const float4 cv = cvs[nt][mt];
                 const float v[4] = {cv.x, cv.y, cv.z, cv.w};
                 float t[4], r[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    t[i] = lowpass ? 0.0f : softplusf(acc[mt][nt][i] + bias);
-                    r[i] = (fabsf(v[i] * sc) >= t[i]) ? v[i] : 0.0f;
+                    if constexpr (MODE == 2) {
+                        const float o = acc[mt][nt][i] + bias;
+                        const float d = fabsf(v[i] * sc) - fmaxf(o, 0.0f);
+                        const float u = __builtin_amdgcn_exp2f(-fabsf(o) * L2E);
+                        float e = 1.0f / 362880.0f;
+                        e = fmaf(e, d, 1.0f / 40320.0f);
+                        e = fmaf(e, d, 1.0f / 5040.0f);
+                        e = fmaf(e, d, 1.0f / 720.0f);
+                        e = fmaf(e, d, 1.0f / 120.0f);
+                        e = fmaf(e, d, 1.0f / 24.0f);
+                        e = fmaf(e, d, 1.0f / 6.0f);
+                        e = fmaf(e, d, 0.5f);
+                        e = fmaf(e, d, 1.0f);
+                        e *= d;
+                        const bool keep = lowpass || d >= 0.75f || (d >= 0.0f && e >= u);
+                        r[i] = keep ? v[i] : 0.0f;
+                    } else {
+                        t[i] = lowpass ? 0.0f : softplusf(acc[mt][nt][i] + bias);
+                        r[i] = (fabsf(v[i] * sc) >= t[i]) ? v[i] : 0.0f;
+                    }
                 }
-                *reinterpret_cast<float4*>(a.out_f + off) = make_float4(r[0], r[1], r[2], r[3]);
-                if (a.tau) *reinterpret_cast<float4*>(a.tau + off) = make_float4(t[0], t[1], t[2], t[3]);
+                *reinterpret_cast<float4*>(op + vo) = make_float4(r[0], r[1], r[2], r[3]);
+                if constexpr (MODE == 5)
+                    *reinterpret_cast<float4*>(a.tau + offs[nt] + vo) = make_float4(t[0], t[1], t[2], t[3]);
             }
         }
         }
@@ -687,6 +772,15 @@ hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream
     }
     if (layer == 4) return conv_t<32, 32, 4>(a, batch, st);  // backward data from 32 gradient channels
     if (layer == 5) return shrink_cinp(K) == 32 ? conv_t<32, 32, 4>(a, batch, st) : conv_t<64, 32, 4>(a, batch, st);
+    if (a.tau) {  // the shrink layer that also writes the thresholds
+        switch (shrink_coutp(K)) {
+            case 16: return conv_t<32, 16, 5>(a, batch, st);
+            case 32: return conv_t<32, 32, 5>(a, batch, st);
+            case 48: return conv_t<32, 48, 5>(a, batch, st);
+            case 64: return conv_t<32, 64, 5>(a, batch, st);
+        }
+        return hipErrorInvalidValue;
+    }
     switch (shrink_coutp(K)) {
         case 16: return conv_t<32, 16, 2>(a, batch, st);
         case 32: return conv_t<32, 32, 2>(a, batch, st);

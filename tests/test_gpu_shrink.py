@@ -61,6 +61,24 @@ def _check(got_c, got_t, c32, sigma, rms, p):
     assert np.all((got_c[amb] == c32[amb]) | (got_c[amb] == 0.0))
 
 
+def _check_decision(got_c, c32, sigma, rms, p, got_c_tau, got_t):
+    """The shrink without the threshold output (it decides without forming tau): against the oracle
+    where _check's decisions are clear (outside the 1e-3 band around the oracle's tau and not between
+    the oracle's tau and the network's own, got_t from the run that writes tau), and against the
+    decisions of the run that writes tau outside a 1e-5 band around that run's tau."""
+    want_c, want_t = OS.shrink(c32.astype(np.float64), sigma, rms, p)
+    az = np.abs(c32.astype(np.float64) / (sigma * rms[:, None, None]))
+    lo = np.minimum(got_t, want_t) * (1 - 1e-6)
+    hi = np.maximum(got_t, want_t) * (1 + 1e-6)
+    between = (az >= lo) & (az <= hi)
+    clear = (np.abs(az - want_t) > 1e-3 * np.maximum(want_t, 1e-3)) & ~between
+    assert clear.mean() > 0.99
+    assert np.array_equal(got_c[clear], want_c[clear])
+    assert np.all((got_c[~clear] == c32[~clear]) | (got_c[~clear] == 0.0))
+    far = np.abs(az - got_t) > 1e-5 * got_t
+    assert np.array_equal(got_c[far], got_c_tau[far])
+
+
 def test_shrink_matches_oracle_128(gpu):
     from paper_2006_04591_amd import ShearletSystem, ShrinkNet
 
@@ -76,9 +94,12 @@ def test_shrink_matches_oracle_128(gpu):
     with ShearletSystem.build(128, 128, 2) as s:
         net = ShrinkNet(s, _params_dict(p))
         out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        out2 = net.apply(_to(c32, gpu), _to(sig, gpu))
         torch.cuda.synchronize()
         for b in range(2):
             _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], ref.rms, p)
+            _check_decision(out2[b].cpu().numpy(), c32[b], sig[b], ref.rms, p, out[b].cpu().numpy(),
+                            tau[b].cpu().numpy())
         assert float(tau[:, :-1].std()) > 0.1  # the network's thresholds do vary
 
 
@@ -121,9 +142,11 @@ def test_shrink_tile_borders_user_bank(gpu):
         assert np.allclose(s.rms, rms, rtol=1e-12)
         net = ShrinkNet(s, _params_dict(p))
         out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        out2 = net.apply(_to(c32, gpu), _to(sig, gpu))
         torch.cuda.synchronize()
         for b in range(3):
             _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], rms, p)
+            _check_decision(out2[b].cpu().numpy(), c32[b], sig[b], rms, p, out[b].cpu().numpy(), tau[b].cpu().numpy())
 
 
 def test_shrink_errors(gpu):
@@ -160,6 +183,8 @@ def test_shrink_wide_channel_counts(gpu, K):
     with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
         net = ShrinkNet(s, _params_dict(p))
         out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        out2 = net.apply(_to(c32, gpu), _to(sig, gpu))
         torch.cuda.synchronize()
         for b in range(2):
             _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], rms, p)
+            _check_decision(out2[b].cpu().numpy(), c32[b], sig[b], rms, p, out[b].cpu().numpy(), tau[b].cpu().numpy())
