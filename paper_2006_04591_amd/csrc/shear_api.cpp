@@ -1276,6 +1276,7 @@ int shear_shrink_apply(shear_system* s, const float* coeffs, float* shrunk, floa
     a.M = M;
     a.scale = scale;
     a.lowpass = K - 1;
+    a.cus = s->cus;
     // layer 1: z = bf16(c scale), staged from the coefficients inside the layer -> h1
     a.coef = coeffs;
     a.W = (const unsigned short*)(p + L.w1);

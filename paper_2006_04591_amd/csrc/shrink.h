@@ -31,6 +31,7 @@ struct ConvArgs {
     const unsigned short* mask_act;    // backward data: saved activation whose relu mask applies
     float* loss;                       // layer 2 training: sum of squared residuals (added)
     float loss_scale, temperature;
+    int cus;  // compute units of the device (grid of the persistent first layer)
 };
 
 // Weight-gradient launch: dy bf16 channel-last with dy_ch channels; input x bf16 channel-last (the packed z

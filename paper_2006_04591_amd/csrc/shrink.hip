@@ -60,20 +60,16 @@ struct Pix {
 
 // LDS of a conv block: the staged input tile; the bf16 output tile (the 32 hidden channels, or the
 // padded gradient planes of layer 2's training epilogue) reuses it once the products are done.
-// The shrink epilogue (MODE 2) works from registers.
+// The shrink epilogue (MODE 2, 5) works from registers.
 // Input channels are staged at most 32 at a time (a layer with 64 input channels stages and
-// multiplies twice), which keeps the tile at 27 KB; the layer that stages from the coefficient
-// planes (COEF_IN) stages all of them at once (49 KB at 64 channels: its registers already hold
-// it to 3 blocks per CU, and one stage-and-multiply phase instead of two saves a barrier and
-// lets the second half's loads start without waiting for the first half's products).
-template <int CINP, bool COEF_IN = false>
+// multiplies twice), which keeps the tile at 27 KB.
+template <int CINP>
 constexpr int staged_ch() {
-    return (CINP > 32 && !COEF_IN) ? 32 : CINP;
+    return CINP > 32 ? 32 : CINP;
 }
-template <int CINP, int OUTC, int MODE, bool COEF_IN = false>
+template <int CINP, int OUTC, int MODE>
 constexpr size_t conv_lds_bytes() {
-    constexpr size_t in = (size_t)HH * HW * Pix<staged_ch<CINP, COEF_IN>()>::value * 2,
-                     out = (size_t)TH * TW * OUTC * 2;
+    constexpr size_t in = (size_t)HH * HW * Pix<staged_ch<CINP>()>::value * 2, out = (size_t)TH * TW * OUTC * 2;
     return (MODE == 2 || MODE == 5 || in >= out) ? in : out;
 }
 
@@ -118,86 +114,6 @@ __device__ __forceinline__ uint2 pack_bf16x4(float a, float b, float c, float d)
     const bf16x2 lo = __builtin_convertvector((f32x2){a, b}, bf16x2);
     const bf16x2 hi = __builtin_convertvector((f32x2){c, d}, bf16x2);
     return make_uint2(__builtin_bit_cast(unsigned, lo), __builtin_bit_cast(unsigned, hi));
-}
-
-// Stages the halo tile of one image straight from the FP32 channel-first coefficient planes:
-// z = bf16(c x scale[b][k]) channel-last, zero beyond the a.cin real channels (the values
-// k_pack_z would write). Work unit: 8 consecutive channels (one 16-byte run of a staged pixel) of
-// 4 consecutive interior pixels of one tile row: 8 aligned 16-byte loads, one per channel plane,
-// become 4 16-byte LDS stores. Lanes take the channel groups fastest: in each load instruction
-// the 8 lanes of one group read the 8 16-byte pieces of one 128-byte row segment of a plane, and
-// in each store the lanes of one pixel write its runs as contiguous bytes. A lane always has the same channel
-// group (256 threads, a multiple of the group count), so it loads its 8 scales once. The two halo
-// columns go the same way with one value per channel. All of a thread's loads are issued before
-// its first LDS store.
-template <int CS>
-__device__ __forceinline__ void stage_coef(const ConvArgs& a, unsigned short* s, int b, int y0, int x0, int cb) {
-    constexpr int PIX = Pix<CS>::value, QW = TW / 4, G = CS / 8;
-    static_assert(CS % 8 == 0 && THREADS % G == 0, "whole channel groups, one per lane");
-    constexpr int TOTAL = G * QW * HH, NIT = (TOTAL + THREADS - 1) / THREADS;
-    constexpr int HTOTAL = G * HH * 2, HNIT = (HTOTAL + THREADS - 1) / THREADS;
-    const int N = a.N, M = a.M, K = a.cin;
-    const int g = (int)threadIdx.x % G;
-    const size_t plane = (size_t)N * M;
-    const int k0 = cb + 8 * g;
-    const float* base = a.coef + ((size_t)b * K + k0) * plane;
-    float sc[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) sc[c] = (k0 + c < K) ? a.scale[b * K + k0 + c] : 0.0f;
-    float h[HNIT][8];
-#pragma unroll
-    for (int j = 0; j < HNIT; ++j) {
-        const int i = (int)threadIdx.x + j * THREADS;
-        const int side = (i / G) % 2, yy = i / (2 * G);
-        const int y = (y0 + yy - 1 + N) & (N - 1), x = side ? (x0 + TW) & (M - 1) : (x0 - 1 + M) & (M - 1);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) h[j][c] = (i < HTOTAL && k0 + c < K) ? base[c * plane + (size_t)y * M + x] : 0.0f;
-    }
-    float4 v[NIT][8];
-#pragma unroll
-    for (int j = 0; j < NIT; ++j) {
-        const int i = (int)threadIdx.x + j * THREADS;
-        const int q = (i / G) % QW, yy = i / (G * QW);
-        const int y = (y0 + yy - 1 + N) & (N - 1);
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            v[j][c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (i < TOTAL && k0 + c < K)
-                v[j][c] = *reinterpret_cast<const float4*>(base + c * plane + (size_t)y * M + x0 + 4 * q);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < NIT; ++j) {
-        const int i = (int)threadIdx.x + j * THREADS;
-        if (i < TOTAL) {
-            const int q = (i / G) % QW, yy = i / (G * QW);
-            unsigned short* d = s + (yy * HW + 1 + 4 * q) * PIX + 8 * g;
-            const float4* w = v[j];
-            const uint2 p0a = pack_bf16x4(w[0].x * sc[0], w[1].x * sc[1], w[2].x * sc[2], w[3].x * sc[3]);
-            const uint2 p0b = pack_bf16x4(w[4].x * sc[4], w[5].x * sc[5], w[6].x * sc[6], w[7].x * sc[7]);
-            const uint2 p1a = pack_bf16x4(w[0].y * sc[0], w[1].y * sc[1], w[2].y * sc[2], w[3].y * sc[3]);
-            const uint2 p1b = pack_bf16x4(w[4].y * sc[4], w[5].y * sc[5], w[6].y * sc[6], w[7].y * sc[7]);
-            const uint2 p2a = pack_bf16x4(w[0].z * sc[0], w[1].z * sc[1], w[2].z * sc[2], w[3].z * sc[3]);
-            const uint2 p2b = pack_bf16x4(w[4].z * sc[4], w[5].z * sc[5], w[6].z * sc[6], w[7].z * sc[7]);
-            const uint2 p3a = pack_bf16x4(w[0].w * sc[0], w[1].w * sc[1], w[2].w * sc[2], w[3].w * sc[3]);
-            const uint2 p3b = pack_bf16x4(w[4].w * sc[4], w[5].w * sc[5], w[6].w * sc[6], w[7].w * sc[7]);
-            *reinterpret_cast<uint4*>(d) = make_uint4(p0a.x, p0a.y, p0b.x, p0b.y);
-            *reinterpret_cast<uint4*>(d + PIX) = make_uint4(p1a.x, p1a.y, p1b.x, p1b.y);
-            *reinterpret_cast<uint4*>(d + 2 * PIX) = make_uint4(p2a.x, p2a.y, p2b.x, p2b.y);
-            *reinterpret_cast<uint4*>(d + 3 * PIX) = make_uint4(p3a.x, p3a.y, p3b.x, p3b.y);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < HNIT; ++j) {
-        const int i = (int)threadIdx.x + j * THREADS;
-        if (i < HTOTAL) {
-            const int side = (i / G) % 2, yy = i / (2 * G);
-            const float* w = h[j];
-            const uint2 pa = pack_bf16x4(w[0] * sc[0], w[1] * sc[1], w[2] * sc[2], w[3] * sc[3]);
-            const uint2 pb = pack_bf16x4(w[4] * sc[4], w[5] * sc[5], w[6] * sc[6], w[7] * sc[7]);
-            *reinterpret_cast<uint4*>(s + (yy * HW + (side ? HW - 1 : 0)) * PIX + 8 * g) = make_uint4(pa.x, pa.y, pb.x, pb.y);
-        }
-    }
 }
 
 // z = bf16(coefficients x scale), channel-first FP32 -> channel-last bf16 [b][y][x][CINP] (zero padded):
@@ -315,32 +231,25 @@ __device__ __forceinline__ int conv_tile() {
 //   bf16 channel-last planes [b][y][x][OUTC] (zero beyond K and on the low-pass plane);
 // MODE 4 (training, backward data): gradient planes -> conv with flipped, transposed weights, times the relu
 //   mask of the saved activation (mask_act > 0) -> bf16 gradient activations.
-// COEF_IN: the input is staged from the coefficients (stage_coef) instead of a.in.
-// Waves per SIMD a conv kernel's registers must allow, where its LDS allows them: the layer staged
-// from the coefficients holds 3 blocks per CU by its LDS (49 KB at 64 channels), the hidden layer 5
-// (27 KB); the prefetched weight fragments would otherwise cost each a wave.
-template <int CINP, int MODE, bool COEF_IN>
+// Waves per SIMD a conv kernel's registers must allow, where its LDS allows them: the hidden layer
+// holds 5 blocks per CU by its LDS (27 KB); the prefetched weight fragments would otherwise cost it
+// a wave.
+template <int CINP, int MODE>
 constexpr int conv_min_waves() {
-    return COEF_IN ? 3 : ((MODE == 1 && CINP == 32) ? 5 : 1);
+    return (MODE == 1 && CINP == 32) ? 5 : 1;
 }
 
-template <int CINP, int COUTP, int MODE, int OUTC = 32, bool COEF_IN = false>
-__global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE, COEF_IN>())) void k_conv3x3(ConvArgs a) {
+template <int CINP, int COUTP, int MODE, int OUTC = 32>
+__global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE>())) void k_conv3x3(ConvArgs a) {
     constexpr int NT = COUTP / 16;
     extern __shared__ unsigned short smem[];
     unsigned short* s_in = smem;
     const int tx = a.M / TW, ty = a.N / TH, tile = conv_tile();
     const int bx = tile % tx, by = (tile / tx) % ty, b = tile / (tx * ty);
     const int x0 = bx * TW, y0 = by * TH;
-    constexpr int CS = staged_ch<CINP, COEF_IN>();
+    constexpr int CS = staged_ch<CINP>();
     static_assert((MODE != 2 && MODE != 5) || CS == CINP, "the shrink layer stages its whole input once");
-    auto stage_part = [&](int cb) {
-        if constexpr (COEF_IN) {
-            stage_coef<CS>(a, s_in, b, y0, x0, cb);
-        } else {
-            stage<CINP, CS>(a, s_in, b, y0, x0, cb);
-        }
-    };
+    auto stage_part = [&](int cb) { stage<CINP, CS>(a, s_in, b, y0, x0, cb); };
     constexpr bool SHRINK = (MODE == 2 || MODE == 5);
     if constexpr (SHRINK) {
         stage_part(0);
@@ -356,11 +265,13 @@ __global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE, COEF_IN>())) v
         // (48 padded channels go in three passes of 16: a pass never reads weight rows past COUTP)
         // MODE 5 writes tau and decides with it. MODE 2 (no tau output) decides without forming
         // tau: with a = |c scale| >= 0, m = max(o, 0), u = e^-|o| in (0, 1] and d = a - m,
-        // softplus(o) = m + log1p(u), so a >= softplus(o) <=> d >= 0 and expm1(d) >= u. Every d
-        // >= 0.75 passes (expm1(0.75) > 1 >= u); below, expm1 is its Taylor polynomial of degree 9
-        // (remainder < 2e-8 relative). One hardware exponential replaces the exponential, logarithm
-        // and reciprocal of softplus, and the decision keeps softplus's relative precision for small
-        // and large thresholds alike.
+        // softplus(o) = m + log1p(u), so a >= softplus(o) <=> expm1(d) >= u. d is clamped to
+        // [0, 0.75] (below 0, expm1 < 0 < u; above, expm1 > 1 >= u), where expm1 is its Taylor
+        // polynomial of degree 9 (remainder < 2e-8 relative), and for o > 0, u is kept above 1e-30
+        // (beyond o = 87 it underflows: then softplus(o) = o in FP32 and the test is d > 0). The
+        // low-pass plane takes o = -inf: u = 0, every coefficient kept. One hardware exponential replaces
+        // softplus's exponential, logarithm and reciprocal, with no branch, and the decision keeps
+        // softplus's relative precision for small and large thresholds alike.
         constexpr int CG = COUTP <= 32 ? COUTP : (COUTP % 32 == 0 ? 32 : 16), NG = CG / 16;
         static_assert(COUTP % CG == 0, "the passes cover the padded output channels exactly");
         constexpr float L2E = 1.44269504088896341f;
@@ -411,9 +322,9 @@ __global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE, COEF_IN>())) v
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     if constexpr (MODE == 2) {
-                        const float o = acc[mt][nt][i] + bias;
-                        const float d = fabsf(v[i] * sc) - fmaxf(o, 0.0f);
-                        const float u = __builtin_amdgcn_exp2f(-fabsf(o) * L2E);
+                        const float o = acc[mt][nt][i] + (lowpass ? -INFINITY : bias);
+                        const float d = fminf(fmaxf(fabsf(v[i] * sc) - fmaxf(o, 0.0f), 0.0f), 0.75f);
+                        const float u = fmaxf(__builtin_amdgcn_exp2f(-fabsf(o) * L2E), o > 0.0f ? 1e-30f : 0.0f);
                         float e = 1.0f / 362880.0f;
                         e = fmaf(e, d, 1.0f / 40320.0f);
                         e = fmaf(e, d, 1.0f / 5040.0f);
@@ -423,9 +334,7 @@ __global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE, COEF_IN>())) v
                         e = fmaf(e, d, 1.0f / 6.0f);
                         e = fmaf(e, d, 0.5f);
                         e = fmaf(e, d, 1.0f);
-                        e *= d;
-                        const bool keep = lowpass || d >= 0.75f || (d >= 0.0f && e >= u);
-                        r[i] = keep ? v[i] : 0.0f;
+                        r[i] = (e * d >= u) ? v[i] : 0.0f;
                     } else {
                         t[i] = lowpass ? 0.0f : softplusf(acc[mt][nt][i] + bias);
                         r[i] = (fabsf(v[i] * sc) >= t[i]) ? v[i] : 0.0f;
@@ -508,6 +417,223 @@ __global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE, COEF_IN>())) v
             out[(((size_t)b * a.N + y0 + py) * a.M + x0 + px) * CH + ch] =
                 *reinterpret_cast<const uint4*>(s_out + p * OUTC + ch * 8);
         }
+    }
+}
+
+// ---------------------------------------------------------------- persistent first layer
+// The first layer (coefficients -> 32 hidden channels) as a persistent kernel: one 512-thread block
+// per CU keeps the layer's weights in LDS and walks a list of 8 x 64-pixel tiles, software
+// pipelined: while the matrix cores work on tile t out of LDS, the FP32 loads of tile t + 1 are
+// in flight in registers; then tile t's bf16 outputs leave through LDS (over the staged tile) and
+// tile t + 1 is converted into the staging buffer. Only these loads and stores use the vector-memory
+// counter, so waiting for the prefetched tile never waits for weight loads, and the stores of
+// tile t (issued after the prefetch) are not waited for. A tile reads 256-byte runs of each
+// coefficient plane (128-byte runs of 8 x 32-pixel tiles measured at half the bandwidth). The tiles
+// of the batch are cut into 8 contiguous ranges, one per XCD (block w runs on XCD w mod 8), so
+// that the halo re-reads of neighbouring tiles hit that XCD's L2.
+constexpr int PTH = 8, PHH = PTH + 2;     // tile rows, with halo
+constexpr int PTW = 64, PHW = PTW + 2;    // tile columns, with halo
+constexpr int PTHREADS = 512;             // 8 wavefronts, one tile row each
+
+template <int CS>
+struct PLds {
+    static constexpr int PIX = Pix<CS>::value;
+    static constexpr int WP = 9 * CS + 8;  // bf16 per output channel of the staged weights (padded)
+    static constexpr size_t in = (size_t)PHH * PHW * PIX * 2, w = (size_t)32 * WP * 2;
+    static constexpr size_t bytes = in + w;
+    static_assert((size_t)PTH * PTW * 32 * 2 <= in, "the output tile fits over the staged tile");
+};
+
+// A tile's FP32 inputs held in registers between their loads and their conversion to LDS.
+template <int CS>
+struct CoefRegs {
+    static constexpr int G = CS / 8, QW = PTW / 4;
+    static constexpr int TOTAL = G * QW * PHH, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
+    static constexpr int HTOTAL = G * PHH * 2, HNIT = (HTOTAL + PTHREADS - 1) / PTHREADS;
+    float4 v[NIT][8];
+    float h[HNIT][8];
+    float sc[8];
+};
+
+// Loads tile (b, y0, x0) in units of 8 consecutive channels (one 16-byte run of a staged pixel) of 4
+// consecutive interior pixels of one row: 8 aligned 16-byte loads, one per channel plane. Lanes
+// take the channel groups fastest: in each load instruction the lanes of one group read
+// consecutive 16-byte pieces of a row of a plane. A lane's channel group is fixed (512 is a
+// multiple of G), and so are its 8 scales within a tile. The two halo columns come one value per
+// channel.
+template <int CS>
+__device__ __forceinline__ void coef_load(const ConvArgs& a, CoefRegs<CS>& r, int b, int y0, int x0) {
+    using R = CoefRegs<CS>;
+    const int N = a.N, M = a.M, K = a.cin;
+    const int g = (int)threadIdx.x % R::G, k0 = 8 * g;
+    const size_t plane = (size_t)N * M;
+    const float* base = a.coef + ((size_t)b * K + k0) * plane;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) r.sc[c] = (k0 + c < K) ? a.scale[b * K + k0 + c] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < R::HNIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        const int side = (i / R::G) % 2, yy = i / (2 * R::G);
+        const int y = (y0 + yy - 1 + N) & (N - 1), x = side ? (x0 + PTW) & (M - 1) : (x0 - 1 + M) & (M - 1);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            r.h[j][c] = (i < R::HTOTAL && k0 + c < K) ? base[c * plane + (size_t)y * M + x] : 0.0f;
+    }
+#pragma unroll
+    for (int j = 0; j < R::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        const int q = (i / R::G) % R::QW, yy = i / (R::G * R::QW);
+        const int y = (y0 + yy - 1 + N) & (N - 1);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            r.v[j][c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (i < R::TOTAL && k0 + c < K)
+                r.v[j][c] = *reinterpret_cast<const float4*>(base + c * plane + (size_t)y * M + x0 + 4 * q);
+        }
+    }
+}
+
+// z = bf16(c scale) of the loaded tile -> the channel-last staging buffer (16-byte runs)
+template <int CS>
+__device__ __forceinline__ void coef_store(const CoefRegs<CS>& r, unsigned short* s) {
+    using R = CoefRegs<CS>;
+    constexpr int PIX = Pix<CS>::value;
+    const int g = (int)threadIdx.x % R::G;
+    const float* sc = r.sc;
+#pragma unroll
+    for (int j = 0; j < R::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        if (i < R::TOTAL) {
+            const int q = (i / R::G) % R::QW, yy = i / (R::G * R::QW);
+            unsigned short* d = s + (yy * PHW + 1 + 4 * q) * PIX + 8 * g;
+            const float4* w = r.v[j];
+            const uint2 p0a = pack_bf16x4(w[0].x * sc[0], w[1].x * sc[1], w[2].x * sc[2], w[3].x * sc[3]);
+            const uint2 p0b = pack_bf16x4(w[4].x * sc[4], w[5].x * sc[5], w[6].x * sc[6], w[7].x * sc[7]);
+            const uint2 p1a = pack_bf16x4(w[0].y * sc[0], w[1].y * sc[1], w[2].y * sc[2], w[3].y * sc[3]);
+            const uint2 p1b = pack_bf16x4(w[4].y * sc[4], w[5].y * sc[5], w[6].y * sc[6], w[7].y * sc[7]);
+            const uint2 p2a = pack_bf16x4(w[0].z * sc[0], w[1].z * sc[1], w[2].z * sc[2], w[3].z * sc[3]);
+            const uint2 p2b = pack_bf16x4(w[4].z * sc[4], w[5].z * sc[5], w[6].z * sc[6], w[7].z * sc[7]);
+            const uint2 p3a = pack_bf16x4(w[0].w * sc[0], w[1].w * sc[1], w[2].w * sc[2], w[3].w * sc[3]);
+            const uint2 p3b = pack_bf16x4(w[4].w * sc[4], w[5].w * sc[5], w[6].w * sc[6], w[7].w * sc[7]);
+            *reinterpret_cast<uint4*>(d) = make_uint4(p0a.x, p0a.y, p0b.x, p0b.y);
+            *reinterpret_cast<uint4*>(d + PIX) = make_uint4(p1a.x, p1a.y, p1b.x, p1b.y);
+            *reinterpret_cast<uint4*>(d + 2 * PIX) = make_uint4(p2a.x, p2a.y, p2b.x, p2b.y);
+            *reinterpret_cast<uint4*>(d + 3 * PIX) = make_uint4(p3a.x, p3a.y, p3b.x, p3b.y);
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < R::HNIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        if (i < R::HTOTAL) {
+            const int side = (i / R::G) % 2, yy = i / (2 * R::G);
+            const float* w = r.h[j];
+            const uint2 pa = pack_bf16x4(w[0] * sc[0], w[1] * sc[1], w[2] * sc[2], w[3] * sc[3]);
+            const uint2 pb = pack_bf16x4(w[4] * sc[4], w[5] * sc[5], w[6] * sc[6], w[7] * sc[7]);
+            *reinterpret_cast<uint4*>(s + (yy * PHW + (side ? PHW - 1 : 0)) * PIX + 8 * g) =
+                make_uint4(pa.x, pa.y, pb.x, pb.y);
+        }
+    }
+}
+
+// The tiles of block w: t0 + j, t0 + j + per, ... < t1, where [t0, t1) is the (w mod 8)-th of 8
+// contiguous ranges of the ntiles tiles, j = w / 8 and per = gridDim.x / 8 (the blocks on one XCD).
+__device__ __forceinline__ void xcd_range(int ntiles, int& first, int& end, int& stride) {
+    const int w = (int)blockIdx.x, per = (int)gridDim.x / 8, x = w % 8, j = w / 8;
+    first = (int)(((long long)x * ntiles) / 8) + j;
+    end = (int)(((long long)(x + 1) * ntiles) / 8);
+    stride = per;
+}
+
+template <int CINP>
+__global__ __launch_bounds__(PTHREADS, 2) void k_conv_coef(ConvArgs a, int ntiles) {
+    constexpr int CS = CINP, PIX = Pix<CS>::value, WP = PLds<CS>::WP, KCN = CS / 32, STEPS = 9 * KCN;
+    extern __shared__ unsigned short smem[];
+    unsigned short* s_in = smem;
+    unsigned short* s_out = smem;  // the output tile, over the staged tile once the products are done
+    unsigned short* s_w = smem + PLds<CS>::in / 2;
+    const int tx = a.M / PTW, ty = a.N / PTH;
+    int t, end, stride;
+    xcd_range(ntiles, t, end, stride);
+    if (t >= end) return;  // the whole block: no tile
+    auto tile_origin = [&](int tile, int& b, int& y0, int& x0) {
+        x0 = (tile % tx) * PTW;
+        y0 = ((tile / tx) % ty) * PTH;
+        b = tile / (tx * ty);
+    };
+    // weights [co][tap][ci] -> LDS rows of WP bf16 (16-byte pieces)
+    for (int i = (int)threadIdx.x; i < 32 * 9 * CS / 8; i += PTHREADS) {
+        const int co = i / (9 * CS / 8), r = i % (9 * CS / 8);
+        *reinterpret_cast<uint4*>(s_w + co * WP + 8 * r) = reinterpret_cast<const uint4*>(a.W)[i];
+    }
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int lr = l % 16, lk = 8 * (l / 16), lm = 4 * (l / 16);
+    float bias[2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) bias[nt] = a.bias[nt * 16 + lr];
+    CoefRegs<CS> r;
+    int b, y0, x0;
+    tile_origin(t, b, y0, x0);
+    coef_load<CS>(a, r, b, y0, x0);
+    coef_store<CS>(r, s_in);
+    int tn = t + stride;
+    if (tn < end) {
+        int bn, yn, xn;
+        tile_origin(tn, bn, yn, xn);
+        coef_load<CS>(a, r, bn, yn, xn);
+    }
+    __syncthreads();
+    for (;;) {
+        // wave w: tile row w, 4 m-tiles of 16 pixels
+        f32x4 acc[4][2];
+        zero_acc(acc);
+#pragma unroll 1
+        for (int it = 0; it < STEPS; ++it) {
+            const int tap = it / KCN, kc = it % KCN, dy = tap / 3, dx = tap % 3;
+            bf16x8 bf[2];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+                bf[nt] = *reinterpret_cast<const bf16x8*>(s_w + (nt * 16 + lr) * WP + tap * CS + kc * 32 + lk);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const bf16x8 afr = *reinterpret_cast<const bf16x8*>(
+                    s_in + ((w + dy) * PHW + 16 * mt + lr + dx) * PIX + kc * 32 + lk);
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bf[nt], acc[mt][nt], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wave is done reading the staged tile
+        // relu(acc + bias) -> bf16 output tile [pixel][32 channels]
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int prow = w * PTW + 16 * mt + lm;
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    s_out[(prow + i) * 32 + nt * 16 + lr] = f2bf(fmaxf(acc[mt][nt][i] + bias[nt], 0.0f));
+        }
+        __syncthreads();  // the output tile is written
+        {
+            uint4* out = reinterpret_cast<uint4*>(a.out_bf);
+            for (int i = (int)threadIdx.x; i < PTH * PTW * 4; i += PTHREADS) {
+                const int ch = i % 4, p = i / 4, px = p % PTW, py = p / PTW;
+                out[(((size_t)b * a.N + y0 + py) * a.M + x0 + px) * 4 + ch] =
+                    *reinterpret_cast<const uint4*>(s_out + p * 32 + ch * 8);
+            }
+        }
+        if (tn >= end) break;
+        __syncthreads();          // the output tile is read
+        coef_store<CS>(r, s_in);  // tile tn, loaded during this tile's products
+        t = tn;
+        tile_origin(t, b, y0, x0);
+        tn = t + stride;
+        if (tn < end) {
+            int bn, yn, xn;
+            tile_origin(tn, bn, yn, xn);
+            coef_load<CS>(a, r, bn, yn, xn);
+        }
+        __syncthreads();  // the next tile is staged
     }
 }
 
@@ -677,17 +803,28 @@ __global__ void k_pack_bias(const float* __restrict__ b, float* __restrict__ out
     if (i < np) out[i] = i < n ? b[i] : 0.0f;
 }
 
-template <int CINP, int COUTP, int MODE, int OUTC = 32, bool COEF_IN = false>
+template <int CINP, int COUTP, int MODE, int OUTC = 32>
 hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
-    const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC, COEF_IN>);
-    const size_t lds = conv_lds_bytes<CINP, OUTC, MODE, COEF_IN>();
+    const void* fn = reinterpret_cast<const void*>(&k_conv3x3<CINP, COUTP, MODE, OUTC>);
+    const size_t lds = conv_lds_bytes<CINP, OUTC, MODE>();
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const size_t blocks = (size_t)batch * (a.N / TH) * (a.M / TW);
-    hipLaunchKernelGGL((k_conv3x3<CINP, COUTP, MODE, OUTC, COEF_IN>), dim3((unsigned)blocks), dim3(THREADS), lds, st,
+    hipLaunchKernelGGL((k_conv3x3<CINP, COUTP, MODE, OUTC>), dim3((unsigned)blocks), dim3(THREADS), lds, st,
                        a);
+    return hipGetLastError();
+}
+
+template <int CINP>
+hipError_t conv_coef_t(const ConvArgs& a, int batch, hipStream_t st) {
+    const void* fn = reinterpret_cast<const void*>(&k_conv_coef<CINP>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLds<CINP>::bytes);
+    if (e != hipSuccess) return e;
+    const int ntiles = batch * (a.N / PTH) * (a.M / PTW);
+    const int blocks = std::max(8, a.cus / 8 * 8);  // one per CU, a multiple of the 8 XCDs
+    hipLaunchKernelGGL((k_conv_coef<CINP>), dim3((unsigned)blocks), dim3(PTHREADS), PLds<CINP>::bytes, st, a, ntiles);
     return hipGetLastError();
 }
 
@@ -754,8 +891,7 @@ hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream
     if (layer == 0) return shrink_cinp(K) == 32 ? conv_t<32, 32, 1>(a, batch, st) : conv_t<64, 32, 1>(a, batch, st);
     if (layer == 1) return conv_t<32, 32, 1>(a, batch, st);
     if (layer == 6)  // layer 1 staged straight from the coefficients (a.coef, a.scale, a.cin = K)
-        return shrink_cinp(K) == 32 ? conv_t<32, 32, 1, 32, true>(a, batch, st)
-                                    : conv_t<64, 32, 1, 32, true>(a, batch, st);
+        return shrink_cinp(K) == 32 ? conv_coef_t<32>(a, batch, st) : conv_coef_t<64>(a, batch, st);
     if (layer == 3) {  // training: last layer with the loss epilogue, gradient planes of shrink_cinp(K) channels
         if (shrink_cinp(K) == 32) {
             switch (shrink_coutp(K)) {
