@@ -335,8 +335,9 @@ int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int 
  * then the inverse's with the chosen forward), on temporary images and
  * coefficients it allocates for the call (batch * (2 + K) * rows * cols
  * floats) and frees before it returns; five interleaved rounds, each
- * candidate keeps the median of its step times. Keeps the fastest of each
- * direction (shear_set_schedule) and reports it through the out-pointers (any
+ * candidate keeps the median of its step times. Keeps, for each direction,
+ * the candidate with the fewest filter groups among those within 1 % of the
+ * fastest median (shear_set_schedule) and reports it through the out-pointers (any
  * may be NULL). Synchronous: waits for the device, allocates the workspace for
  * batch if needed, uses the null stream; per-launch timing is paused during the
  * call. SHEAR_E_NOMEM if the temporary buffers cannot be allocated. Drops any

@@ -1035,17 +1035,24 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
             }
         }
         if (e != hipSuccess || call_rc != SHEAR_OK) break;
-        size_t pick_i = 0;
-        float pick = -1.0f;
+        std::vector<float> med(cand.size(), -1.0f);
+        float best = -1.0f;
         for (size_t ci = 0; ci < cand.size(); ++ci) {
             std::vector<float> t = times[ci];
             if (t.empty()) continue;
             std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
-            const float med = t[t.size() / 2];
-            if (pick < 0.0f || med < pick) {
-                pick = med;
+            med[ci] = t[t.size() / 2];
+            if (best < 0.0f || med[ci] < best) best = med[ci];
+        }
+        // a filter split adds work (the forward repeats a panel's column FFT per group, the inverse
+        // writes and adds partial sums), so it is taken only where it is measurably faster: among
+        // the candidates within 1 % of the fastest step, the fewest groups, then the fastest
+        size_t pick_i = 0;
+        for (size_t ci = 0; ci < cand.size(); ++ci) {
+            if (med[ci] < 0.0f || med[ci] > 1.01f * best) continue;
+            if (med[pick_i] < 0.0f || med[pick_i] > 1.01f * best || cand[ci].kg < cand[pick_i].kg ||
+                (cand[ci].kg == cand[pick_i].kg && med[ci] < med[pick_i]))
                 pick_i = ci;
-            }
         }
         (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = cand[pick_i].pw;
         (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = cand[pick_i].kg;

@@ -149,6 +149,30 @@ def test_shrink_tile_borders_user_bank(gpu):
             _check_decision(out2[b].cpu().numpy(), c32[b], sig[b], rms, p, out[b].cpu().numpy(), tau[b].cpu().numpy())
 
 
+def test_shrink_uneven_tile_ranges(gpu):
+    """16 x 128 planes, B=3, K=5: the first layer's 12 tiles of 8 x 64 pixels split into 8 per-XCD
+    ranges of one or two tiles, most blocks of its one-per-CU grid without a tile."""
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say("case: shrink 16x128 K=5 B=3 (uneven tile ranges)")
+    rng = np.random.default_rng(14)
+    S = np.fft.fft2(rng.standard_normal((5, 16, 128)))
+    rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+    c32 = (rng.standard_normal((3, 5, 16, 128)) * 30.0 * rms[None, :, None, None]).astype(np.float32)
+    sig = np.array([12.0, 25.0, 45.0])
+    p = OS.init_params(5, seed=9, tau0=2.0)
+    p.W3 *= 10.0
+    p = OS.ShrinkParams(p.W1, p.b1 + 0.1, p.W2, p.b2 - 0.05, p.W3, p.b3)
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        net = ShrinkNet(s, _params_dict(p))
+        out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        out2 = net.apply(_to(c32, gpu), _to(sig, gpu))
+        torch.cuda.synchronize()
+        for b in range(3):
+            _check(out[b].cpu().numpy(), tau[b].cpu().numpy(), c32[b], sig[b], rms, p)
+            _check_decision(out2[b].cpu().numpy(), c32[b], sig[b], rms, p, out[b].cpu().numpy(), tau[b].cpu().numpy())
+
+
 def test_shrink_errors(gpu):
     from paper_2006_04591_amd import ShearError, ShearletSystem, ShrinkNet
 
