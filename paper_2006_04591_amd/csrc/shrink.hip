@@ -152,7 +152,7 @@ __device__ __forceinline__ void zero_acc(f32x4 (&acc)[4][NT]) {
 // out[pixel][co] accumulators of a wavefront: 4 m-tiles (16 pixels of one row) x NT n-tiles, added
 // to acc: output channels co0 .. co0 + COUTP - 1 of the packed weights (CINP input channels per
 // tap), input channels cb .. cb + CS - 1 staged in s.
-template <int CINP, int CS, int COUTP, bool PIPE = true>
+template <int CINP, int CS, int COUTP, int PD = 2>
 __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, f32x4 (&acc)[4][COUTP / 16], int co0,
                                     int cb) {
     constexpr int PIX = Pix<CS>::value, NT = COUTP / 16;
@@ -178,13 +178,12 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
                 acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bf[nt], acc[mt][nt], 0, 0, 0);
         }
     };
-    if constexpr (PIPE) {
+    if constexpr (PD > 0) {
         // fully unrolled; the weight fragments are loaded PD steps ahead of their products, so that
         // their latency (an L2 hit, several times one step's products) overlaps PD steps of products
         // ((PD + 1) x NT x 4 VGPRs). A scheduling barrier after each step's loads keeps them there:
         // with a distance of one step and no barrier, the scheduler moved each load down to its use
         // and every step waited for L2.
-        constexpr int PD = 2;
         bf16x8 bq[STEPS][NT];
 #pragma unroll
         for (int it = 0; it < PD && it < STEPS; ++it)
@@ -200,7 +199,8 @@ __device__ __forceinline__ void mma(const ConvArgs& a, const unsigned short* s, 
             step(it, bq[it]);
         }
     } else {
-        // one step at a time (the shrink epilogue's kernel keeps its registers for waves)
+        // one step at a time (the shrink layer: one step ahead measured no faster, 0.565 against
+        // 0.572 ms, as its registers then hold it to 3 waves per SIMD instead of 4)
 #pragma unroll 1
         for (int it = 0; it < STEPS; ++it) {
             bf16x8 bf[NT];
@@ -304,7 +304,7 @@ __global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE>())) void k_con
         }
         f32x4 acc[4][NG];
         zero_acc(acc);
-        mma<CINP, CS, CG, false>(a, s_in, acc, c0, 0);
+        mma<CINP, CS, CG, 0>(a, s_in, acc, c0, 0);
 #pragma unroll
         for (int nt = 0; nt < NG; ++nt) {
             const int k = c0 + nt * 16 + lr;
