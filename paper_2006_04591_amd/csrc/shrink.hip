@@ -637,6 +637,207 @@ __global__ __launch_bounds__(PTHREADS, 2) void k_conv_coef(ConvArgs a, int ntile
     }
 }
 
+// ---------------------------------------------------------------- persistent shrink layer
+// The last layer with the shrink decision (no tau output) in the persistent form of k_conv_coef:
+// one 512-thread block per CU keeps the layer's weights in LDS and walks its XCD's range of
+// 8 x 64-pixel tiles. Per tile, the staged hidden activations serve CG output channels at a time;
+// each pass's FP32 coefficients come into LDS as 256-byte row runs, are decided there in the matrix
+// cores' lane layout (c kept or zeroed in place) and leave as 256-byte row runs. The next pass's
+// coefficients, and during the first pass the next tile's activations, are in flight in registers
+// while the matrix cores work.
+template <int COUTP>
+struct SLds {
+    static constexpr int CG = COUTP <= 32 ? COUTP : (COUTP % 32 == 0 ? 32 : 16);  // channels per pass
+    static constexpr int PIX = Pix<32>::value;
+    static constexpr int WP = 9 * 32 + 8;            // bf16 per output channel of the staged weights
+    static constexpr int CP = PTH * PTW + 4;         // floats per channel of the coefficient pass buffer
+    static constexpr size_t h = (size_t)PHH * PHW * PIX * 2, w = (size_t)COUTP * WP * 2,
+                            c = (size_t)CG * CP * 4;
+    static constexpr size_t bytes = h + w + c;
+};
+
+// The hidden activations of tile (b, y0, x0) with its halo, [pixel][32 channels] bf16, in 16-byte units.
+struct HidRegs {
+    static constexpr int TOTAL = PHH * PHW * 4, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
+    uint4 v[NIT];
+};
+
+__device__ __forceinline__ void hid_load(const ConvArgs& a, HidRegs& r, int b, int y0, int x0) {
+    const int N = a.N, M = a.M;
+    const uint4* in = reinterpret_cast<const uint4*>(a.in);
+#pragma unroll
+    for (int j = 0; j < HidRegs::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        r.v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (i < HidRegs::TOTAL) {
+            const int ch = i % 4, p = i / 4, xx = p % PHW, yy = p / PHW;
+            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
+            r.v[j] = in[(((size_t)b * N + y) * M + x) * 4 + ch];
+        }
+    }
+}
+
+__device__ __forceinline__ void hid_store(const HidRegs& r, unsigned short* s) {
+    constexpr int PIX = Pix<32>::value;
+#pragma unroll
+    for (int j = 0; j < HidRegs::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        if (i < HidRegs::TOTAL) {
+            const int ch = i % 4, p = i / 4;
+            *reinterpret_cast<uint4*>(s + p * PIX + ch * 8) = r.v[j];
+        }
+    }
+}
+
+// One pass's coefficients of tile (b, y0, x0): channels c0 .. c0 + CG - 1 (those below K), 8 rows of
+// 64 pixels, as 16-byte units with 16 lanes per 256-byte row run.
+template <int CG>
+struct PassRegs {
+    static constexpr int TOTAL = CG * PTH * (PTW / 4), NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
+    float4 v[NIT];
+};
+
+template <int CG>
+__device__ __forceinline__ void pass_load(const ConvArgs& a, PassRegs<CG>& r, int b, int y0, int x0, int c0) {
+#pragma unroll
+    for (int j = 0; j < PassRegs<CG>::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        const int q = i % (PTW / 4), yy = (i / (PTW / 4)) % PTH, kl = i / (PTH * PTW / 4), k = c0 + kl;
+        r.v[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (i < PassRegs<CG>::TOTAL && k < a.cout)
+            r.v[j] = *reinterpret_cast<const float4*>(a.coef + (((size_t)b * a.cout + k) * a.N + y0 + yy) * a.M + x0 + 4 * q);
+    }
+}
+
+template <int COUTP>
+__global__ __launch_bounds__(PTHREADS, 2) void k_conv_shrink(ConvArgs a, int ntiles) {
+    using L = SLds<COUTP>;
+    constexpr int CG = L::CG, NG = CG / 16, NP = COUTP / CG, PIX = L::PIX, WP = L::WP, CP = L::CP;
+    static_assert(COUTP % CG == 0, "the passes cover the padded output channels exactly");
+    constexpr float L2E = 1.44269504088896341f;
+    extern __shared__ unsigned short smem[];
+    unsigned short* s_h = smem;
+    unsigned short* s_w = smem + L::h / 2;
+    float* s_c = reinterpret_cast<float*>(smem + (L::h + L::w) / 2);
+    const int tx = a.M / PTW, ty = a.N / PTH;
+    int t, end, stride;
+    xcd_range(ntiles, t, end, stride);
+    if (t >= end) return;  // the whole block: no tile
+    auto tile_origin = [&](int tile, int& b, int& y0, int& x0) {
+        x0 = (tile % tx) * PTW;
+        y0 = ((tile / tx) % ty) * PTH;
+        b = tile / (tx * ty);
+    };
+    // weights [co][tap][ci] (COUTP rows, zero beyond K) -> LDS rows of WP bf16
+    for (int i = (int)threadIdx.x; i < COUTP * 9 * 32 / 8; i += PTHREADS) {
+        const int co = i / (9 * 32 / 8), r = i % (9 * 32 / 8);
+        *reinterpret_cast<uint4*>(s_w + co * WP + 8 * r) = reinterpret_cast<const uint4*>(a.W)[i];
+    }
+    const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    const int lr = l % 16, lk = 8 * (l / 16), lm = 4 * (l / 16);
+    HidRegs hr;
+    PassRegs<CG> pr;
+    int b, y0, x0;
+    tile_origin(t, b, y0, x0);
+    hid_load(a, hr, b, y0, x0);
+    pass_load<CG>(a, pr, b, y0, x0, 0);
+    hid_store(hr, s_h);
+    int tn = t + stride, bn = 0, yn = 0, xn = 0;
+    if (tn < end) tile_origin(tn, bn, yn, xn);
+    for (;;) {
+#pragma unroll 1
+        for (int p = 0; p < NP; ++p) {
+            const int c0 = p * CG;
+            // this pass's coefficients -> LDS [channel][row][pixel] (after the previous pass's copy-out
+            // has read the buffer: the barrier at the end of each pass)
+#pragma unroll
+            for (int j = 0; j < PassRegs<CG>::NIT; ++j) {
+                const int i = (int)threadIdx.x + j * PTHREADS;
+                if (i < PassRegs<CG>::TOTAL) {
+                    const int q = i % (PTW / 4), yy = (i / (PTW / 4)) % PTH, kl = i / (PTH * PTW / 4);
+                    *reinterpret_cast<float4*>(s_c + kl * CP + yy * PTW + 4 * q) = pr.v[j];
+                }
+            }
+            __syncthreads();  // coefficients (and, in the first pass, the activations) staged
+            // next loads: the following pass's coefficients, or the next tile's first pass and activations
+            if (p + 1 < NP) {
+                pass_load<CG>(a, pr, b, y0, x0, c0 + CG);
+            } else if (tn < end) {
+                hid_load(a, hr, bn, yn, xn);
+                pass_load<CG>(a, pr, bn, yn, xn, 0);
+            }
+            f32x4 acc[4][NG];
+            zero_acc(acc);
+#pragma unroll 1
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+                bf16x8 bf[NG];
+#pragma unroll
+                for (int nt = 0; nt < NG; ++nt)
+                    bf[nt] = *reinterpret_cast<const bf16x8*>(s_w + (c0 + nt * 16 + lr) * WP + tap * 32 + lk);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const bf16x8 afr = *reinterpret_cast<const bf16x8*>(s_h + ((w + dy) * PHW + 16 * mt + lr + dx) * PIX + lk);
+#pragma unroll
+                    for (int nt = 0; nt < NG; ++nt)
+                        acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr, bf[nt], acc[mt][nt], 0, 0, 0);
+                }
+            }
+            // the decision of k_conv3x3's MODE 2, on the staged coefficients, in place
+#pragma unroll
+            for (int nt = 0; nt < NG; ++nt) {
+                const int kl = nt * 16 + lr, k = c0 + kl;
+                if (k >= a.cout) continue;
+                const bool lowpass = (k == a.lowpass);
+                const float bias = lowpass ? -INFINITY : a.bias[k];
+                const float sc = a.scale[b * a.cout + k];
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    float4* cp = reinterpret_cast<float4*>(s_c + kl * CP + w * PTW + 16 * mt + lm);
+                    const float4 cv = *cp;
+                    const float v[4] = {cv.x, cv.y, cv.z, cv.w};
+                    float r[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const float o = acc[mt][nt][i] + bias;
+                        const float d = fminf(fmaxf(fabsf(v[i] * sc) - fmaxf(o, 0.0f), 0.0f), 0.75f);
+                        const float u = fmaxf(__builtin_amdgcn_exp2f(-fabsf(o) * L2E), o > 0.0f ? 1e-30f : 0.0f);
+                        float e = 1.0f / 362880.0f;
+                        e = fmaf(e, d, 1.0f / 40320.0f);
+                        e = fmaf(e, d, 1.0f / 5040.0f);
+                        e = fmaf(e, d, 1.0f / 720.0f);
+                        e = fmaf(e, d, 1.0f / 120.0f);
+                        e = fmaf(e, d, 1.0f / 24.0f);
+                        e = fmaf(e, d, 1.0f / 6.0f);
+                        e = fmaf(e, d, 0.5f);
+                        e = fmaf(e, d, 1.0f);
+                        r[i] = (e * d >= u) ? v[i] : 0.0f;
+                    }
+                    *cp = make_float4(r[0], r[1], r[2], r[3]);
+                }
+            }
+            __syncthreads();  // the pass's shrunk coefficients are in LDS
+#pragma unroll
+            for (int j = 0; j < PassRegs<CG>::NIT; ++j) {
+                const int i = (int)threadIdx.x + j * PTHREADS;
+                const int q = i % (PTW / 4), yy = (i / (PTW / 4)) % PTH, kl = i / (PTH * PTW / 4), k = c0 + kl;
+                if (i < PassRegs<CG>::TOTAL && k < a.cout)
+                    *reinterpret_cast<float4*>(a.out_f + (((size_t)b * a.cout + k) * a.N + y0 + yy) * a.M + x0 + 4 * q) =
+                        *reinterpret_cast<const float4*>(s_c + kl * CP + yy * PTW + 4 * q);
+            }
+            if (p + 1 < NP || tn < end) __syncthreads();  // the copy-out has read the buffer
+        }
+        if (tn >= end) break;
+        hid_store(hr, s_h);  // the next tile's activations (every wave is past its products)
+        t = tn;
+        b = bn;
+        y0 = yn;
+        x0 = xn;
+        tn = t + stride;
+        if (tn < end) tile_origin(tn, bn, yn, xn);
+    }
+}
+
 // ---------------------------------------------------------------- weight gradients
 // dW[co][tap][ci] = sum over pixels p of dy[co](p) x[ci](p + tap offset): an MFMA GEMM with
 // M = output channels, N = (tap, input channel), K = pixels (one 32-pixel tile row per step).
@@ -828,6 +1029,17 @@ hipError_t conv_coef_t(const ConvArgs& a, int batch, hipStream_t st) {
     return hipGetLastError();
 }
 
+template <int COUTP>
+hipError_t conv_shrink_t(const ConvArgs& a, int batch, hipStream_t st) {
+    const void* fn = reinterpret_cast<const void*>(&k_conv_shrink<COUTP>);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)SLds<COUTP>::bytes);
+    if (e != hipSuccess) return e;
+    const int ntiles = batch * (a.N / PTH) * (a.M / PTW);
+    const int blocks = std::max(8, a.cus / 8 * 8);  // one per CU, a multiple of the 8 XCDs
+    hipLaunchKernelGGL((k_conv_shrink<COUTP>), dim3((unsigned)blocks), dim3(PTHREADS), SLds<COUTP>::bytes, st, a, ntiles);
+    return hipGetLastError();
+}
+
 template <int CINP, int COUTP>
 hipError_t wgrad_t(const WgradArgs& a, int blocks, hipStream_t st) {
     const void* fn = reinterpret_cast<const void*>(&k_wgrad<CINP, COUTP>);
@@ -918,10 +1130,10 @@ hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream
         return hipErrorInvalidValue;
     }
     switch (shrink_coutp(K)) {
-        case 16: return conv_t<32, 16, 2>(a, batch, st);
-        case 32: return conv_t<32, 32, 2>(a, batch, st);
-        case 48: return conv_t<32, 48, 2>(a, batch, st);
-        case 64: return conv_t<32, 64, 2>(a, batch, st);
+        case 16: return conv_shrink_t<16>(a, batch, st);
+        case 32: return conv_shrink_t<32>(a, batch, st);
+        case 48: return conv_shrink_t<48>(a, batch, st);
+        case 64: return conv_shrink_t<64>(a, batch, st);
     }
     return hipErrorInvalidValue;
 }
