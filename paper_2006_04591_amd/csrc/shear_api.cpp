@@ -1184,6 +1184,7 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
     a.M = M;
     a.scale = scale;
     a.lowpass = K - 1;
+    a.cus = s->cus;
     a.in = zp;
     a.W = (const unsigned short*)(pk + L.w1);
     a.bias = (const float*)(pk + L.b1);

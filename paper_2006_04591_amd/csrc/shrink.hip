@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 namespace shear {
 namespace {
@@ -428,9 +429,10 @@ __global__ __launch_bounds__(THREADS, (conv_min_waves<CINP, MODE>())) void k_con
 // tile t + 1 is converted into the staging buffer. Only these loads and stores use the vector-memory
 // counter, so waiting for the prefetched tile never waits for weight loads, and the stores of
 // tile t (issued after the prefetch) are not waited for. A tile reads 256-byte runs of each
-// coefficient plane (128-byte runs of 8 x 32-pixel tiles measured at half the bandwidth). The tiles
+// coefficient plane (16 x 32-pixel tiles, 128-byte runs, measured 0.49 against 0.44 ms). The tiles
 // of the batch are cut into 8 contiguous ranges, one per XCD (block w runs on XCD w mod 8), so
-// that the halo re-reads of neighbouring tiles hit that XCD's L2.
+// that the halo re-reads of neighbouring tiles hit that XCD's L2. The hidden layer (32 bf16
+// channels in, 32 out) runs in the same kernel with its own staging.
 constexpr int PTH = 8, PHH = PTH + 2;     // tile rows, with halo
 constexpr int PTW = 64, PHW = PTW + 2;    // tile columns, with halo
 constexpr int PTHREADS = 512;             // 8 wavefronts, one tile row each
@@ -535,6 +537,39 @@ __device__ __forceinline__ void coef_store(const CoefRegs<CS>& r, unsigned short
     }
 }
 
+// The hidden activations of tile (b, y0, x0) with its halo, [pixel][32 channels] bf16, in 16-byte units.
+struct HidRegs {
+    static constexpr int TOTAL = PHH * PHW * 4, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
+    uint4 v[NIT];
+};
+
+__device__ __forceinline__ void hid_load(const ConvArgs& a, HidRegs& r, int b, int y0, int x0) {
+    const int N = a.N, M = a.M;
+    const uint4* in = reinterpret_cast<const uint4*>(a.in);
+#pragma unroll
+    for (int j = 0; j < HidRegs::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        r.v[j] = make_uint4(0u, 0u, 0u, 0u);
+        if (i < HidRegs::TOTAL) {
+            const int ch = i % 4, p = i / 4, xx = p % PHW, yy = p / PHW;
+            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
+            r.v[j] = in[(((size_t)b * N + y) * M + x) * 4 + ch];
+        }
+    }
+}
+
+__device__ __forceinline__ void hid_store(const HidRegs& r, unsigned short* s) {
+    constexpr int PIX = Pix<32>::value;
+#pragma unroll
+    for (int j = 0; j < HidRegs::NIT; ++j) {
+        const int i = (int)threadIdx.x + j * PTHREADS;
+        if (i < HidRegs::TOTAL) {
+            const int ch = i % 4, p = i / 4;
+            *reinterpret_cast<uint4*>(s + p * PIX + ch * 8) = r.v[j];
+        }
+    }
+}
+
 // The tiles of block w: t0 + j, t0 + j + per, ... < t1, where [t0, t1) is the (w mod 8)-th of 8
 // contiguous ranges of the ntiles tiles, j = w / 8 and per = gridDim.x / 8 (the blocks on one XCD).
 __device__ __forceinline__ void xcd_range(int ntiles, int& first, int& end, int& stride) {
@@ -544,9 +579,27 @@ __device__ __forceinline__ void xcd_range(int ntiles, int& first, int& end, int&
     stride = per;
 }
 
-template <int CINP>
-__global__ __launch_bounds__(PTHREADS, 2) void k_conv_coef(ConvArgs a, int ntiles) {
+// FROM_COEF: the first layer (input: the FP32 coefficient planes, normalised and rounded on staging);
+// else the hidden layer (input: the bf16 activations of the first, CINP = 32).
+template <int CINP, bool FROM_COEF>
+__global__ __launch_bounds__(PTHREADS, FROM_COEF ? 2 : 4) void k_conv_relu(ConvArgs a, int ntiles) {
     constexpr int CS = CINP, PIX = Pix<CS>::value, WP = PLds<CS>::WP, KCN = CS / 32, STEPS = 9 * KCN;
+    static_assert(FROM_COEF || CINP == 32, "the hidden layer has 32 input channels");
+    using Regs = typename std::conditional<FROM_COEF, CoefRegs<CS>, HidRegs>::type;
+    auto load = [&](Regs& r, int b, int y0, int x0) {
+        if constexpr (FROM_COEF) {
+            coef_load<CS>(a, r, b, y0, x0);
+        } else {
+            hid_load(a, r, b, y0, x0);
+        }
+    };
+    auto store = [&](const Regs& r, unsigned short* s) {
+        if constexpr (FROM_COEF) {
+            coef_store<CS>(r, s);
+        } else {
+            hid_store(r, s);
+        }
+    };
     extern __shared__ unsigned short smem[];
     unsigned short* s_in = smem;
     unsigned short* s_out = smem;  // the output tile, over the staged tile once the products are done
@@ -570,16 +623,16 @@ __global__ __launch_bounds__(PTHREADS, 2) void k_conv_coef(ConvArgs a, int ntile
     float bias[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) bias[nt] = a.bias[nt * 16 + lr];
-    CoefRegs<CS> r;
+    Regs r;
     int b, y0, x0;
     tile_origin(t, b, y0, x0);
-    coef_load<CS>(a, r, b, y0, x0);
-    coef_store<CS>(r, s_in);
+    load(r, b, y0, x0);
+    store(r, s_in);
     int tn = t + stride;
     if (tn < end) {
         int bn, yn, xn;
         tile_origin(tn, bn, yn, xn);
-        coef_load<CS>(a, r, bn, yn, xn);
+        load(r, bn, yn, xn);
     }
     __syncthreads();
     for (;;) {
@@ -623,22 +676,22 @@ __global__ __launch_bounds__(PTHREADS, 2) void k_conv_coef(ConvArgs a, int ntile
             }
         }
         if (tn >= end) break;
-        __syncthreads();          // the output tile is read
-        coef_store<CS>(r, s_in);  // tile tn, loaded during this tile's products
+        __syncthreads();  // the output tile is read
+        store(r, s_in);   // tile tn, loaded during this tile's products
         t = tn;
         tile_origin(t, b, y0, x0);
         tn = t + stride;
         if (tn < end) {
             int bn, yn, xn;
             tile_origin(tn, bn, yn, xn);
-            coef_load<CS>(a, r, bn, yn, xn);
+            load(r, bn, yn, xn);
         }
         __syncthreads();  // the next tile is staged
     }
 }
 
 // ---------------------------------------------------------------- persistent shrink layer
-// The last layer with the shrink decision (no tau output) in the persistent form of k_conv_coef:
+// The last layer with the shrink decision (no tau output) in the persistent form of k_conv_relu:
 // one 512-thread block per CU keeps the layer's weights in LDS and walks its XCD's range of
 // 8 x 64-pixel tiles. Per tile, the staged hidden activations serve CG output channels at a time;
 // each pass's FP32 coefficients come into LDS as 256-byte row runs, are decided there in the matrix
@@ -655,39 +708,6 @@ struct SLds {
                             c = (size_t)CG * CP * 4;
     static constexpr size_t bytes = h + w + c;
 };
-
-// The hidden activations of tile (b, y0, x0) with its halo, [pixel][32 channels] bf16, in 16-byte units.
-struct HidRegs {
-    static constexpr int TOTAL = PHH * PHW * 4, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
-    uint4 v[NIT];
-};
-
-__device__ __forceinline__ void hid_load(const ConvArgs& a, HidRegs& r, int b, int y0, int x0) {
-    const int N = a.N, M = a.M;
-    const uint4* in = reinterpret_cast<const uint4*>(a.in);
-#pragma unroll
-    for (int j = 0; j < HidRegs::NIT; ++j) {
-        const int i = (int)threadIdx.x + j * PTHREADS;
-        r.v[j] = make_uint4(0u, 0u, 0u, 0u);
-        if (i < HidRegs::TOTAL) {
-            const int ch = i % 4, p = i / 4, xx = p % PHW, yy = p / PHW;
-            const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
-            r.v[j] = in[(((size_t)b * N + y) * M + x) * 4 + ch];
-        }
-    }
-}
-
-__device__ __forceinline__ void hid_store(const HidRegs& r, unsigned short* s) {
-    constexpr int PIX = Pix<32>::value;
-#pragma unroll
-    for (int j = 0; j < HidRegs::NIT; ++j) {
-        const int i = (int)threadIdx.x + j * PTHREADS;
-        if (i < HidRegs::TOTAL) {
-            const int ch = i % 4, p = i / 4;
-            *reinterpret_cast<uint4*>(s + p * PIX + ch * 8) = r.v[j];
-        }
-    }
-}
 
 // One pass's coefficients of tile (b, y0, x0): channels c0 .. c0 + CG - 1 (those below K), 8 rows of
 // 64 pixels, as 16-byte units with 16 lanes per 256-byte row run.
@@ -1018,14 +1038,17 @@ hipError_t conv_t(const ConvArgs& a, int batch, hipStream_t st) {
     return hipGetLastError();
 }
 
-template <int CINP>
-hipError_t conv_coef_t(const ConvArgs& a, int batch, hipStream_t st) {
-    const void* fn = reinterpret_cast<const void*>(&k_conv_coef<CINP>);
+template <int CINP, bool FROM_COEF>
+hipError_t conv_relu_t(const ConvArgs& a, int batch, hipStream_t st) {
+    const void* fn = reinterpret_cast<const void*>(&k_conv_relu<CINP, FROM_COEF>);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLds<CINP>::bytes);
     if (e != hipSuccess) return e;
     const int ntiles = batch * (a.N / PTH) * (a.M / PTW);
-    const int blocks = std::max(8, a.cus / 8 * 8);  // one per CU, a multiple of the 8 XCDs
-    hipLaunchKernelGGL((k_conv_coef<CINP>), dim3((unsigned)blocks), dim3(PTHREADS), PLds<CINP>::bytes, st, a, ntiles);
+    // blocks per CU its registers and LDS allow (first layer: 187 VGPRs, 132 KB; hidden layer: 106
+    // VGPRs, 72 KB), a multiple of the 8 XCDs
+    const int blocks = (FROM_COEF ? 1 : 2) * std::max(8, a.cus / 8 * 8);
+    hipLaunchKernelGGL((k_conv_relu<CINP, FROM_COEF>), dim3((unsigned)blocks), dim3(PTHREADS), PLds<CINP>::bytes, st,
+                       a, ntiles);
     return hipGetLastError();
 }
 
@@ -1101,9 +1124,9 @@ hipError_t launch_inv_scale(const float* sigma, const float* rms, float* out, in
 
 hipError_t launch_conv(int layer, int K, const ConvArgs& a, int batch, hipStream_t st) {
     if (layer == 0) return shrink_cinp(K) == 32 ? conv_t<32, 32, 1>(a, batch, st) : conv_t<64, 32, 1>(a, batch, st);
-    if (layer == 1) return conv_t<32, 32, 1>(a, batch, st);
+    if (layer == 1) return conv_relu_t<32, false>(a, batch, st);  // h1 -> h2 (persistent)
     if (layer == 6)  // layer 1 staged straight from the coefficients (a.coef, a.scale, a.cin = K)
-        return shrink_cinp(K) == 32 ? conv_coef_t<32>(a, batch, st) : conv_coef_t<64>(a, batch, st);
+        return shrink_cinp(K) == 32 ? conv_relu_t<32, true>(a, batch, st) : conv_relu_t<64, true>(a, batch, st);
     if (layer == 3) {  // training: last layer with the loss epilogue, gradient planes of shrink_cinp(K) channels
         if (shrink_cinp(K) == 32) {
             switch (shrink_coutp(K)) {
