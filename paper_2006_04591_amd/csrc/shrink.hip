@@ -446,26 +446,27 @@ struct PLds {
     static_assert((size_t)PTH * PTW * 32 * 2 <= in, "the output tile fits over the staged tile");
 };
 
-// A tile's FP32 inputs held in registers between their loads and their conversion to LDS.
-template <int CS>
+// Staged rows R0 .. R0 + NR - 1 of a tile's FP32 inputs (staged row yy is image row y0 + yy - 1),
+// held in registers between their loads and their conversion to LDS.
+template <int CS, int NR>
 struct CoefRegs {
     static constexpr int G = CS / 8, QW = PTW / 4;
-    static constexpr int TOTAL = G * QW * PHH, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
-    static constexpr int HTOTAL = G * PHH * 2, HNIT = (HTOTAL + PTHREADS - 1) / PTHREADS;
+    static constexpr int TOTAL = G * QW * NR, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
+    static constexpr int HTOTAL = G * NR * 2, HNIT = (HTOTAL + PTHREADS - 1) / PTHREADS;
     float4 v[NIT][8];
     float h[HNIT][8];
     float sc[8];
 };
 
-// Loads tile (b, y0, x0) in units of 8 consecutive channels (one 16-byte run of a staged pixel) of 4
-// consecutive interior pixels of one row: 8 aligned 16-byte loads, one per channel plane. Lanes
-// take the channel groups fastest: in each load instruction the lanes of one group read
-// consecutive 16-byte pieces of a row of a plane. A lane's channel group is fixed (512 is a
-// multiple of G), and so are its 8 scales within a tile. The two halo columns come one value per
-// channel.
-template <int CS>
-__device__ __forceinline__ void coef_load(const ConvArgs& a, CoefRegs<CS>& r, int b, int y0, int x0) {
-    using R = CoefRegs<CS>;
+// Loads staged rows R0 .. R0 + NR - 1 of tile (b, y0, x0) in units of 8 consecutive channels (one
+// 16-byte run of a staged pixel) of 4 consecutive interior pixels of one row: 8 aligned 16-byte
+// loads, one per channel plane. Lanes take the channel groups fastest: in each load instruction the
+// lanes of one group read consecutive 16-byte pieces of a row of a plane. A lane's channel group is
+// fixed (512 is a multiple of G), and so are its 8 scales within a tile. The two halo columns come
+// one value per channel.
+template <int CS, int NR>
+__device__ __forceinline__ void coef_load(const ConvArgs& a, CoefRegs<CS, NR>& r, int b, int y0, int x0, int R0) {
+    using R = CoefRegs<CS, NR>;
     const int N = a.N, M = a.M, K = a.cin;
     const int g = (int)threadIdx.x % R::G, k0 = 8 * g;
     const size_t plane = (size_t)N * M;
@@ -475,7 +476,7 @@ __device__ __forceinline__ void coef_load(const ConvArgs& a, CoefRegs<CS>& r, in
 #pragma unroll
     for (int j = 0; j < R::HNIT; ++j) {
         const int i = (int)threadIdx.x + j * PTHREADS;
-        const int side = (i / R::G) % 2, yy = i / (2 * R::G);
+        const int side = (i / R::G) % 2, yy = R0 + i / (2 * R::G);
         const int y = (y0 + yy - 1 + N) & (N - 1), x = side ? (x0 + PTW) & (M - 1) : (x0 - 1 + M) & (M - 1);
 #pragma unroll
         for (int c = 0; c < 8; ++c)
@@ -484,7 +485,7 @@ __device__ __forceinline__ void coef_load(const ConvArgs& a, CoefRegs<CS>& r, in
 #pragma unroll
     for (int j = 0; j < R::NIT; ++j) {
         const int i = (int)threadIdx.x + j * PTHREADS;
-        const int q = (i / R::G) % R::QW, yy = i / (R::G * R::QW);
+        const int q = (i / R::G) % R::QW, yy = R0 + i / (R::G * R::QW);
         const int y = (y0 + yy - 1 + N) & (N - 1);
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
@@ -495,10 +496,10 @@ __device__ __forceinline__ void coef_load(const ConvArgs& a, CoefRegs<CS>& r, in
     }
 }
 
-// z = bf16(c scale) of the loaded tile -> the channel-last staging buffer (16-byte runs)
-template <int CS>
-__device__ __forceinline__ void coef_store(const CoefRegs<CS>& r, unsigned short* s) {
-    using R = CoefRegs<CS>;
+// z = bf16(c scale) of the loaded rows -> the channel-last staging buffer (16-byte runs)
+template <int CS, int NR>
+__device__ __forceinline__ void coef_store(const CoefRegs<CS, NR>& r, unsigned short* s, int R0) {
+    using R = CoefRegs<CS, NR>;
     constexpr int PIX = Pix<CS>::value;
     const int g = (int)threadIdx.x % R::G;
     const float* sc = r.sc;
@@ -506,7 +507,7 @@ __device__ __forceinline__ void coef_store(const CoefRegs<CS>& r, unsigned short
     for (int j = 0; j < R::NIT; ++j) {
         const int i = (int)threadIdx.x + j * PTHREADS;
         if (i < R::TOTAL) {
-            const int q = (i / R::G) % R::QW, yy = i / (R::G * R::QW);
+            const int q = (i / R::G) % R::QW, yy = R0 + i / (R::G * R::QW);
             unsigned short* d = s + (yy * PHW + 1 + 4 * q) * PIX + 8 * g;
             const float4* w = r.v[j];
             const uint2 p0a = pack_bf16x4(w[0].x * sc[0], w[1].x * sc[1], w[2].x * sc[2], w[3].x * sc[3]);
@@ -527,7 +528,7 @@ __device__ __forceinline__ void coef_store(const CoefRegs<CS>& r, unsigned short
     for (int j = 0; j < R::HNIT; ++j) {
         const int i = (int)threadIdx.x + j * PTHREADS;
         if (i < R::HTOTAL) {
-            const int side = (i / R::G) % 2, yy = i / (2 * R::G);
+            const int side = (i / R::G) % 2, yy = R0 + i / (2 * R::G);
             const float* w = r.h[j];
             const uint2 pa = pack_bf16x4(w[0] * sc[0], w[1] * sc[1], w[2] * sc[2], w[3] * sc[3]);
             const uint2 pb = pack_bf16x4(w[4] * sc[4], w[5] * sc[5], w[6] * sc[6], w[7] * sc[7]);
@@ -537,35 +538,39 @@ __device__ __forceinline__ void coef_store(const CoefRegs<CS>& r, unsigned short
     }
 }
 
-// The hidden activations of tile (b, y0, x0) with its halo, [pixel][32 channels] bf16, in 16-byte units.
+// Staged rows R0 .. R0 + NR - 1 of a tile's hidden activations with the halo columns, [pixel][32
+// channels] bf16, in 16-byte units.
+template <int NR>
 struct HidRegs {
-    static constexpr int TOTAL = PHH * PHW * 4, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
+    static constexpr int TOTAL = NR * PHW * 4, NIT = (TOTAL + PTHREADS - 1) / PTHREADS;
     uint4 v[NIT];
 };
 
-__device__ __forceinline__ void hid_load(const ConvArgs& a, HidRegs& r, int b, int y0, int x0) {
+template <int NR>
+__device__ __forceinline__ void hid_load(const ConvArgs& a, HidRegs<NR>& r, int b, int y0, int x0, int R0) {
     const int N = a.N, M = a.M;
     const uint4* in = reinterpret_cast<const uint4*>(a.in);
 #pragma unroll
-    for (int j = 0; j < HidRegs::NIT; ++j) {
+    for (int j = 0; j < HidRegs<NR>::NIT; ++j) {
         const int i = (int)threadIdx.x + j * PTHREADS;
         r.v[j] = make_uint4(0u, 0u, 0u, 0u);
-        if (i < HidRegs::TOTAL) {
-            const int ch = i % 4, p = i / 4, xx = p % PHW, yy = p / PHW;
+        if (i < HidRegs<NR>::TOTAL) {
+            const int ch = i % 4, p = i / 4, xx = p % PHW, yy = R0 + p / PHW;
             const int y = (y0 + yy - 1 + N) & (N - 1), x = (x0 + xx - 1 + M) & (M - 1);
             r.v[j] = in[(((size_t)b * N + y) * M + x) * 4 + ch];
         }
     }
 }
 
-__device__ __forceinline__ void hid_store(const HidRegs& r, unsigned short* s) {
+template <int NR>
+__device__ __forceinline__ void hid_store(const HidRegs<NR>& r, unsigned short* s, int R0) {
     constexpr int PIX = Pix<32>::value;
 #pragma unroll
-    for (int j = 0; j < HidRegs::NIT; ++j) {
+    for (int j = 0; j < HidRegs<NR>::NIT; ++j) {
         const int i = (int)threadIdx.x + j * PTHREADS;
-        if (i < HidRegs::TOTAL) {
+        if (i < HidRegs<NR>::TOTAL) {
             const int ch = i % 4, p = i / 4;
-            *reinterpret_cast<uint4*>(s + p * PIX + ch * 8) = r.v[j];
+            *reinterpret_cast<uint4*>(s + (R0 * PHW + p) * PIX + ch * 8) = r.v[j];
         }
     }
 }
@@ -579,38 +584,79 @@ __device__ __forceinline__ void xcd_range(int ntiles, int& first, int& end, int&
     stride = per;
 }
 
+// The contiguous chunk [first, end) of tiles of block w: the j-th of per equal parts of the (w mod 8)-th
+// of 8 contiguous ranges of the ntiles tiles (j = w / 8, per = gridDim.x / 8, the blocks on one XCD).
+__device__ __forceinline__ void xcd_chunk(int ntiles, int& first, int& end) {
+    const int w = (int)blockIdx.x, per = (int)gridDim.x / 8, x = w % 8, j = w / 8;
+    const long long lo = ((long long)x * ntiles) / 8, hi = ((long long)(x + 1) * ntiles) / 8;
+    first = (int)(lo + ((hi - lo) * j) / per);
+    end = (int)(lo + ((hi - lo) * (j + 1)) / per);
+}
+
 // FROM_COEF: the first layer (input: the FP32 coefficient planes, normalised and rounded on staging);
 // else the hidden layer (input: the bf16 activations of the first, CINP = 32).
+// The first layer walks its block's chunk of tiles down vertical strips (tile index: rows of tiles
+// fastest, then strips of 64 columns, then images), as a sliding window: the staged tile's last two
+// rows (its bottom halo and last row) are the next tile's first two, so they move up in LDS and
+// only 8 new rows are loaded per tile (10 at the top of a strip); neighbouring chunks of an XCD run
+// down neighbouring strips together, so the halo columns hit that XCD's L2 (0.449 -> 0.406 ms).
+// The hidden layer, whose tiles are a quarter of the bytes, takes its tiles interleaved over the
+// XCD's blocks and loads all 10 rows (the sliding window's extra barrier and copy made it slower:
+// 0.123 -> 0.138 ms).
 template <int CINP, bool FROM_COEF>
 __global__ __launch_bounds__(PTHREADS, FROM_COEF ? 2 : 4) void k_conv_relu(ConvArgs a, int ntiles) {
     constexpr int CS = CINP, PIX = Pix<CS>::value, WP = PLds<CS>::WP, KCN = CS / 32, STEPS = 9 * KCN;
     static_assert(FROM_COEF || CINP == 32, "the hidden layer has 32 input channels");
-    using Regs = typename std::conditional<FROM_COEF, CoefRegs<CS>, HidRegs>::type;
-    auto load = [&](Regs& r, int b, int y0, int x0) {
+    constexpr bool SLIDE = FROM_COEF;
+    constexpr int R0 = SLIDE ? 2 : 0, NR = PHH - R0;  // staged rows loaded per tile (the prefetch)
+    using Regs8 = typename std::conditional<FROM_COEF, CoefRegs<CS, NR>, HidRegs<NR>>::type;
+    using Regs2 = typename std::conditional<FROM_COEF, CoefRegs<CS, 2>, HidRegs<2>>::type;
+    auto load8 = [&](Regs8& r, int b, int y0, int x0) {  // staged rows R0 .. 9
         if constexpr (FROM_COEF) {
-            coef_load<CS>(a, r, b, y0, x0);
+            coef_load<CS, NR>(a, r, b, y0, x0, R0);
         } else {
-            hid_load(a, r, b, y0, x0);
+            hid_load<NR>(a, r, b, y0, x0, R0);
         }
     };
-    auto store = [&](const Regs& r, unsigned short* s) {
+    auto store8 = [&](const Regs8& r, unsigned short* s) {
         if constexpr (FROM_COEF) {
-            coef_store<CS>(r, s);
+            coef_store<CS, NR>(r, s, R0);
         } else {
-            hid_store(r, s);
+            hid_store<NR>(r, s, R0);
+        }
+    };
+    auto stage_top = [&](unsigned short* s, int b, int y0, int x0) {  // staged rows 0, 1 straight from memory
+        Regs2 r2;
+        if constexpr (FROM_COEF) {
+            coef_load<CS, 2>(a, r2, b, y0, x0, 0);
+            coef_store<CS, 2>(r2, s, 0);
+        } else {
+            hid_load<2>(a, r2, b, y0, x0, 0);
+            hid_store<2>(r2, s, 0);
         }
     };
     extern __shared__ unsigned short smem[];
     unsigned short* s_in = smem;
-    unsigned short* s_out = smem;  // the output tile, over the staged tile once the products are done
+    unsigned short* s_out = smem;  // the output tile, over the staged tile's first rows once the products are done
     unsigned short* s_w = smem + PLds<CS>::in / 2;
+    static_assert((size_t)PTH * PTW * 32 * 2 <= (size_t)(PHH - 2) * PHW * PIX * 2,
+                  "the output tile leaves the staged tile's last two rows intact");
     const int tx = a.M / PTW, ty = a.N / PTH;
-    int t, end, stride;
-    xcd_range(ntiles, t, end, stride);
+    int t, end, stride = 1;
+    if constexpr (SLIDE) {
+        xcd_chunk(ntiles, t, end);
+    } else {
+        xcd_range(ntiles, t, end, stride);
+    }
     if (t >= end) return;  // the whole block: no tile
     auto tile_origin = [&](int tile, int& b, int& y0, int& x0) {
-        x0 = (tile % tx) * PTW;
-        y0 = ((tile / tx) % ty) * PTH;
+        if constexpr (SLIDE) {
+            y0 = (tile % ty) * PTH;
+            x0 = ((tile / ty) % tx) * PTW;
+        } else {
+            x0 = (tile % tx) * PTW;
+            y0 = ((tile / tx) % ty) * PTH;
+        }
         b = tile / (tx * ty);
     };
     // weights [co][tap][ci] -> LDS rows of WP bf16 (16-byte pieces)
@@ -619,20 +665,20 @@ __global__ __launch_bounds__(PTHREADS, FROM_COEF ? 2 : 4) void k_conv_relu(ConvA
         *reinterpret_cast<uint4*>(s_w + co * WP + 8 * r) = reinterpret_cast<const uint4*>(a.W)[i];
     }
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
-    const int lr = l % 16, lk = 8 * (l / 16), lm = 4 * (l / 16);
+    const int lr = l % 16, lm = 4 * (l / 16), lk = 8 * (l / 16);
     float bias[2];
 #pragma unroll
     for (int nt = 0; nt < 2; ++nt) bias[nt] = a.bias[nt * 16 + lr];
-    Regs r;
+    Regs8 r;
     int b, y0, x0;
     tile_origin(t, b, y0, x0);
-    load(r, b, y0, x0);
-    store(r, s_in);
-    int tn = t + stride;
-    if (tn < end) {
+    if constexpr (SLIDE) stage_top(s_in, b, y0, x0);
+    load8(r, b, y0, x0);
+    store8(r, s_in);
+    if (t + stride < end) {
         int bn, yn, xn;
-        tile_origin(tn, bn, yn, xn);
-        load(r, bn, yn, xn);
+        tile_origin(t + stride, bn, yn, xn);
+        load8(r, bn, yn, xn);
     }
     __syncthreads();
     for (;;) {
@@ -675,16 +721,37 @@ __global__ __launch_bounds__(PTHREADS, FROM_COEF ? 2 : 4) void k_conv_relu(ConvA
                     *reinterpret_cast<const uint4*>(s_out + p * 32 + ch * 8);
             }
         }
-        if (tn >= end) break;
+        if (t + stride >= end) break;
+        const int tn = t + stride;
+        int bn, yn, xn;
+        tile_origin(tn, bn, yn, xn);
         __syncthreads();  // the output tile is read
-        store(r, s_in);   // tile tn, loaded during this tile's products
+        if (!SLIDE) {
+            // every tile stages all its rows (below)
+        } else if (yn != 0) {
+            // the next tile continues the strip: its first two staged rows are this one's last two
+            constexpr int U = 2 * PHW * PIX / 8;  // 16-byte units of two staged rows
+            static_assert(U > PTHREADS && U <= 3 * PTHREADS, "two staged rows are 2 or 3 units per thread");
+            const uint4* src = reinterpret_cast<const uint4*>(s_in + PTH * PHW * PIX);
+            uint4* dst = reinterpret_cast<uint4*>(s_in);
+            const int i0 = (int)threadIdx.x, i1 = i0 + PTHREADS, i2 = i0 + 2 * PTHREADS;
+            const uint4 m0 = src[i0], m1 = src[min(i1, U - 1)], m2 = src[min(i2, U - 1)];
+            __syncthreads();  // rows 8 and 9 are read before the new rows overwrite them
+            dst[i0] = m0;
+            if (i1 < U) dst[i1] = m1;
+            if (i2 < U) dst[i2] = m2;
+        } else {
+            stage_top(s_in, bn, yn, xn);  // the top of a strip: its first two rows from memory
+        }
+        store8(r, s_in);  // staged rows R0 .. 9 of tile tn, loaded during this tile's products
         t = tn;
-        tile_origin(t, b, y0, x0);
-        tn = t + stride;
-        if (tn < end) {
-            int bn, yn, xn;
-            tile_origin(tn, bn, yn, xn);
-            load(r, bn, yn, xn);
+        b = bn;
+        y0 = yn;
+        x0 = xn;
+        if (t + stride < end) {
+            int bq, yq, xq;
+            tile_origin(t + stride, bq, yq, xq);
+            load8(r, bq, yq, xq);
         }
         __syncthreads();  // the next tile is staged
     }
@@ -755,13 +822,13 @@ __global__ __launch_bounds__(PTHREADS, 2) void k_conv_shrink(ConvArgs a, int nti
     }
     const int w = threadIdx.x / 64, l = threadIdx.x % 64;
     const int lr = l % 16, lk = 8 * (l / 16), lm = 4 * (l / 16);
-    HidRegs hr;
+    HidRegs<PHH> hr;
     PassRegs<CG> pr;
     int b, y0, x0;
     tile_origin(t, b, y0, x0);
-    hid_load(a, hr, b, y0, x0);
+    hid_load<PHH>(a, hr, b, y0, x0, 0);
     pass_load<CG>(a, pr, b, y0, x0, 0);
-    hid_store(hr, s_h);
+    hid_store<PHH>(hr, s_h, 0);
     int tn = t + stride, bn = 0, yn = 0, xn = 0;
     if (tn < end) tile_origin(tn, bn, yn, xn);
     for (;;) {
@@ -783,7 +850,7 @@ __global__ __launch_bounds__(PTHREADS, 2) void k_conv_shrink(ConvArgs a, int nti
             if (p + 1 < NP) {
                 pass_load<CG>(a, pr, b, y0, x0, c0 + CG);
             } else if (tn < end) {
-                hid_load(a, hr, bn, yn, xn);
+                hid_load<PHH>(a, hr, bn, yn, xn, 0);
                 pass_load<CG>(a, pr, bn, yn, xn, 0);
             }
             f32x4 acc[4][NG];
@@ -848,7 +915,7 @@ __global__ __launch_bounds__(PTHREADS, 2) void k_conv_shrink(ConvArgs a, int nti
             if (p + 1 < NP || tn < end) __syncthreads();  // the copy-out has read the buffer
         }
         if (tn >= end) break;
-        hid_store(hr, s_h);  // the next tile's activations (every wave is past its products)
+        hid_store<PHH>(hr, s_h, 0);  // the next tile's activations (every wave is past its products)
         t = tn;
         b = bn;
         y0 = yn;
