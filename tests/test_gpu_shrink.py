@@ -173,6 +173,38 @@ def test_shrink_uneven_tile_ranges(gpu):
             _check_decision(out2[b].cpu().numpy(), c32[b], sig[b], rms, p, out[b].cpu().numpy(), tau[b].cpu().numpy())
 
 
+def test_shrink_sliding_window_strips(gpu):
+    """512 x 256 planes, B=3, K=49 (user bank): 768 first-layer tiles of 8 x 64 pixels, so each
+    block of the one-per-CU grid walks a chunk of about three tiles down a 64-column strip (the
+    staged rows moved up in LDS, 8 new rows loaded), some chunks crossing from the bottom of one
+    strip to the top of the next; image 0 against the oracle, both shrink epilogues."""
+    from paper_2006_04591_amd import ShearletSystem, ShrinkNet
+
+    _say("case: shrink 512x256 K=49 B=3 (sliding window across strips)")
+    rng = np.random.default_rng(15)
+    K, N, M = 49, 512, 256
+    S = np.fft.fft2(rng.standard_normal((K, N, M)))
+    rms = np.sqrt(np.mean(np.abs(S) ** 2, axis=(1, 2)))
+    c32 = (rng.standard_normal((3, K, N, M)) * 30.0 * rms[None, :, None, None]).astype(np.float32)
+    sig = np.array([20.0, 35.0, 15.0])
+    p = OS.init_params(K, seed=11, tau0=2.0)
+    p.W3 *= 10.0
+    p = OS.ShrinkParams(p.W1, p.b1 + 0.1, p.W2, p.b2 - 0.05, p.W3, p.b3)
+    with ShearletSystem.from_spectra(np.fft.fftshift(S, axes=(1, 2))) as s:
+        net = ShrinkNet(s, _params_dict(p))
+        out, tau = net.apply(_to(c32, gpu), _to(sig, gpu), tau=True)
+        out2 = net.apply(_to(c32, gpu), _to(sig, gpu))
+        torch.cuda.synchronize()
+        _check(out[0].cpu().numpy(), tau[0].cpu().numpy(), c32[0], sig[0], rms, p)
+        _check_decision(out2[0].cpu().numpy(), c32[0], sig[0], rms, p, out[0].cpu().numpy(), tau[0].cpu().numpy())
+        # the other images: both epilogues decide alike away from the thresholds
+        for b in (1, 2):
+            az = np.abs(c32[b].astype(np.float64) / (sig[b] * rms[:, None, None]))
+            t = tau[b].cpu().numpy()
+            far = np.abs(az - t) > 1e-5 * t
+            assert np.array_equal(out2[b].cpu().numpy()[far], out[b].cpu().numpy()[far])
+
+
 def test_shrink_errors(gpu):
     from paper_2006_04591_amd import ShearError, ShearletSystem, ShrinkNet
 
