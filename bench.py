@@ -43,7 +43,7 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
+def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool, plane_fwd: bool = False) -> float:
     """Algorithmic bytes per transform call of each kernel kind at this workload (a call with chunked
     launches splits these bytes evenly over its launches).
 
@@ -51,33 +51,38 @@ def kernel_algorithmic_bytes(kind: str, K: int, real_filters: bool) -> float:
     forward transform, and read the coefficients and the filter bank and write
     the images in the inverse. Each of these compulsory transfers is attributed
     to the kernel that performs it; exchange intermediates count as overhead.
+    With the whole-plane forward (plane_fwd), its plane kernel reads the filters and
+    writes the coefficients, and the forward's column pass only forms the images'
+    column spectra.
     """
     img = B * N * M * 4
     coef = B * K * N * M * 4
     filt = K * N * (M // 2 + 1) * (4 if real_filters else 8)
     return {
         "rows_r2c_images": img,
-        "cols_fwd": filt,
+        "cols_fwd": 0 if plane_fwd else filt,
         "rows_c2r_coeffs": coef,
         "rows_r2c_coeffs": coef,
         "cols_inv": filt,
         "rows_c2r_images": img,
         "rows_thresh": 0,
+        "plane_fwd": coef + filt,
     }[kind]
 
 
-def exchange_bytes(kind: str, K: int) -> float:
+def exchange_bytes(kind: str, K: int, plane_fwd: bool = False) -> float:
     """Bytes of the packed exchange planes a kernel kind reads and writes per transform call
     (the intermediates between the row and column stages)."""
     plane = N * (M // 2) * 8
     return {
         "rows_r2c_images": B * plane,
-        "cols_fwd": B * plane + B * K * plane,
+        "cols_fwd": 2 * B * plane if plane_fwd else B * plane + B * K * plane,
         "rows_c2r_coeffs": B * K * plane,
         "rows_r2c_coeffs": B * K * plane,
         "cols_inv": B * K * plane + B * plane,
         "rows_c2r_images": B * plane,
         "rows_thresh": 2 * B * K * plane,
+        "plane_fwd": B * plane,  # the images' column spectra
     }.get(kind, 0.0)
 
 
@@ -721,12 +726,13 @@ def main() -> int:
     units = B * N * M * K / 1e6
     value = units / (ms_step / 1e3)
     kernels = {}
+    plane_fwd = rec.get("plane_fwd", (0, 0.0))[0] > 0
     for kind, (n, tot) in rec.items():
         if n == 0:
             continue
         avg = tot / n
-        ab = kernel_algorithmic_bytes(kind, K, real_filters) * args.steps / n  # per launch
-        xb = exchange_bytes(kind, K) * args.steps / n
+        ab = kernel_algorithmic_bytes(kind, K, real_filters, plane_fwd) * args.steps / n  # per launch
+        xb = exchange_bytes(kind, K, plane_fwd) * args.steps / n
         kernels[kind] = {"launches": n, "avg_ms": avg, "share": tot / ms_total, "algorithmic_bytes_per_launch": ab,
                          "algorithmic_GBs": ab / (avg / 1e3) / 1e9, "exchange_bytes_per_launch": xb,
                          "exchange_GBs": xb / (avg / 1e3) / 1e9}

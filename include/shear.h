@@ -296,7 +296,10 @@ int shear_shrink_train_step(shear_system* s, const float* c_noisy, const float* 
 #define SHEAR_KERNEL_COLS_INV 4        /* inverse/adjoint: column FFT, x filter, sum over k, IFFT */
 #define SHEAR_KERNEL_ROWS_C2R_IMAGES 5 /* inverse/adjoint: row inverse FFT -> images   */
 #define SHEAR_KERNEL_ROWS_THRESH 6     /* denoising: row inverse FFT, hard threshold, row FFT (in place) */
-#define SHEAR_KERNEL_KINDS 7
+#define SHEAR_KERNEL_PLANE_FWD 7       /* forward, whole-plane form: filter, column IFFT and row
+                                          inverse FFT of one plane per workgroup (its column
+                                          spectra pass counts as SHEAR_KERNEL_COLS_FWD) */
+#define SHEAR_KERNEL_KINDS 8
 
 /* Per-launch timing (tracing). While enabled, every kernel launch of the
  * system is bracketed by two hipEvents recorded on the caller's stream. */
@@ -309,6 +312,15 @@ int shear_profile_read(shear_system* s, int* launches, double* total_ms);
 
 /* Column-pass schedule of the separate-launch kernels:
  *   pw_fwd / pw_inv: columns per block (16 or 8; 16 needs cols >= 32);
+ *     pw_fwd = cols / 2 (the whole packed plane per workgroup) selects, for
+ *     shear_forward, the whole-plane forward where it is compiled (256 x 256
+ *     systems with real filter sets): one workgroup filters a plane,
+ *     transforms its columns and rows on chip and writes only the
+ *     coefficients, so no exchange planes pass through memory; the panel
+ *     schedule is kept for the other column passes (denoising, inpainting,
+ *     shear_forward_noalloc), and pw_fwd = 8 or 16 returns shear_forward to
+ *     it. The column IFFT then runs as 16 x 16 (four steps), so results agree
+ *     with the panel form to rounding; kg_fwd and pc_fwd do not apply to it;
  *   kg_fwd / kg_inv: filter groups (1..K: the K filters of a column panel are
  *     split over that many blocks, so that small batches fill the device; the
  *     inverse then adds the groups' partial sums in group order);
@@ -329,7 +341,8 @@ int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int 
 /* Autotuner: chooses the column-pass schedule of each direction among every
  * compiled panel width, filter split in {1, 2, 4, 8} (at most K; the forward
  * also tries 16 and 32 when batch * cols/16 is below the device's compute
- * units) and points per thread (default and alternative, where there is one).
+ * units) and points per thread (default and alternative, where there is one),
+ * and for the forward also the whole-plane form where it is compiled.
  * Each candidate is timed inside whole shear_forward + shear_inverse steps at
  * this batch size (the forward's candidates with the current inverse schedule,
  * then the inverse's with the chosen forward), on temporary images and
@@ -338,7 +351,9 @@ int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int 
  * candidate keeps the median of its step times. Keeps, for each direction,
  * the candidate with the fewest filter groups among those within 1 % of the
  * fastest median (shear_set_schedule) and reports it through the out-pointers (any
- * may be NULL). Synchronous: waits for the device, allocates the workspace for
+ * may be NULL); the whole-plane forward is taken where its median is below the
+ * chosen panel schedule's (pw_fwd then reports cols / 2, and the panel
+ * schedule stays set for the other column passes). Synchronous: waits for the device, allocates the workspace for
  * batch if needed, uses the null stream; per-launch timing is paused during the
  * call. SHEAR_E_NOMEM if the temporary buffers cannot be allocated. Drops any
  * captured inpainting graph. */

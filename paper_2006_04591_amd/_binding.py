@@ -415,7 +415,7 @@ class ShearletSystem:
 
     # ------------------------------------------------------------ tracing
     KERNEL_KINDS = ("rows_r2c_images", "cols_fwd", "rows_c2r_coeffs", "rows_r2c_coeffs", "cols_inv", "rows_c2r_images",
-                    "rows_thresh")
+                    "rows_thresh", "plane_fwd")
 
     def profile(self, on: bool = True) -> None:
         """Brackets every launch with hipEvents on the caller's stream (shear_profile_enable)."""

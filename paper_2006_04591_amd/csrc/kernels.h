@@ -21,6 +21,7 @@ struct DevPlan {
     int kg_inv = 1;
     int pc_fwd = 0;           // points per thread of the column FFTs (0: col_points_default(N); else
     int pc_inv = 0;           // col_points_alternative(N), a different radix sequence)
+    bool plane_fwd = false;   // shear_forward uses launch_plane_fwd (where plane_fwd_supported)
 };
 
 // Points per thread of the N-point column FFTs: the default, and the alternative the column-pass
@@ -68,6 +69,21 @@ hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nim
 // part: cols_inv_part_elems(d, nimg) float2 of scratch (may be null when that is 0).
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
                            hipStream_t st);
+
+// Whole-plane forward (one workgroup per (image, filter) plane, its transposition on chip),
+// available for 256 x 256 systems with real filter sets. Its operands are residue-major: element
+// (xi, j) of an N x L packed plane at ((xi mod 16) (N / 16) + xi / 16) L + j.
+// launch_plane_filters writes the forward filter set (K x (L + 1) x N floats, column-major, packed
+// column 0's mirrored-term filter in column L) in that layout, per filter N x L floats and then the
+// N mirrored-term floats (the same size); launch_cols_spec turns the packed row spectra A (as
+// launch_cols_fwd takes them) into the column spectra Xr = scale * colFFT(A) (nimg x N x L float2);
+// launch_plane_fwd then writes the coefficient planes out (nimg x K x N x M): the values of
+// launch_cols_fwd followed by launch_rows_c2r (scale 1), up to rounding.
+bool plane_fwd_supported(const DevPlan& d);
+hipError_t launch_plane_filters(const DevPlan& d, const float* filt, float* fr, hipStream_t st);
+hipError_t launch_cols_spec(const DevPlan& d, const float2* A, float2* Xr, int nimg, float scale, hipStream_t st);
+hipError_t launch_plane_fwd(const DevPlan& d, const float2* Xr, float* out, int nimg, const float* fr,
+                            hipStream_t st);
 
 bool size_supported(int n);
 

@@ -610,6 +610,234 @@ __global__ void k_zero_u32(unsigned* p, int n) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
 }
 
+// ---------------------------------------------------------------- whole-plane forward
+// One workgroup per (image, filter) plane: the column IFFT of filter_k (.) X and the row c2r of
+// the result both stay on chip, so the forward writes only the coefficients (no exchange planes).
+// The N-point column IFFT runs as N = NA x NB (four steps): with xi = NB a + b and
+// n = c + NA d, first an NA-point IDFT over a for each (column, b), then the twiddle
+// e^{+2 pi i b c / N}, then an NB-point IDFT over b for each (column, c), which gives rows
+// n = c + NA d, d < NB. After the first step the rows of each residue c depend only on that
+// residue's values, so the plane is finished CR residues (CR NB rows) at a time in LDS while the
+// first step's other residues wait in registers.
+// The image spectra and the filters are read in a residue-major layout, element (b, a, j) of a
+// plane at (b NA + a) L + j (b = xi mod NB, a = xi / NB, j the packed column), so that a
+// wavefront of the first step (one b, 64 consecutive columns) loads whole 512-byte runs and its
+// twiddles are wave-uniform.
+template <int N, int M>
+struct PlaneCfg {
+    static constexpr int L = M / 2;
+    static constexpr int NA = 16, NB = N / NA;
+    static constexpr int CR = 8;                   // residues per round
+    static constexpr int ROUNDS = NA / CR;
+    static constexpr int ROWS = CR * NB;           // plane rows in LDS per round
+    static constexpr int THREADS = ROWS / 2 * 16;  // rows: 16 threads per pair of rows
+    static constexpr int PITCH = L + L / 16 + 1;   // a pair of rows holds an M-point FFT scratch (M + M/16)
+    static constexpr int HALVES = L / 64;          // first step: 64 columns per wavefront, HALVES passes
+    // + the row FFT's twiddles, packed column 0 of X and its mirrored-term filter
+    static constexpr size_t LDS = ((size_t)ROWS * PITCH + M + N) * sizeof(float2) + N * sizeof(float);
+    static_assert(NB == 16 && ROUNDS == 2, "four-step split");
+    static_assert(THREADS == 64 * NB && CR * L == THREADS, "thread roles");
+    static_assert(2 * PITCH >= M + M / 16, "row-pair FFT scratch");
+};
+
+// Xr[b] = scale * colFFT(A[b]) in the residue-major layout (N x L float2 per image); the panel's
+// spectra pass through LDS so that each run of 16 columns is written whole.
+template <int N, int PW, int PP>
+__global__ __launch_bounds__((ColCfg<N, PW, PP>::THREADS)) void k_cols_spec(const float2* __restrict__ A,
+                                                                      float2* __restrict__ Xr, int L, int npan,
+                                                                      const float2* __restrict__ twN, float scale) {
+    constexpr int P = ColCfg<N, PW, PP>::P, T = N / P, THR = ColCfg<N, PW, PP>::THREADS;
+    constexpr int NA = 16, NB = N / NA, SP = PW + 1;
+    static_assert((size_t)N * SP * sizeof(float2) <= ColCfg<N, PW, PP>::LDS, "staging fits the FFT scratch");
+    extern __shared__ float2 lds[];
+    const int pan = blockIdx.x % npan, b = blockIdx.x / npan;
+    const int tid = (int)threadIdx.x;
+    float2 xh[P];
+    col_fwd_setup<N, P, PW>(A + (size_t)b * L * N, pan * PW, xh, lds, scale, twN, tid);
+    const int t = tid % T, c = tid / T;
+#pragma unroll
+    for (int q = 0; q < P; ++q) lds[(t + T * q) * SP + c] = xh[q];
+    __syncthreads();
+    float2* o = Xr + (size_t)b * L * N + pan * PW;
+#pragma unroll
+    for (int i = 0; i < N * PW / THR; ++i) {
+        const int e = tid + THR * i;
+        const int cc = e % PW, ra = e / PW;  // ra = bb NA + a
+        const int xi = NB * (ra % NA) + ra / NA;
+        o[(size_t)ra * L + cc] = lds[xi * SP + cc];
+    }
+}
+
+// Filters of one forward set in the residue-major layout: per filter N x L floats, then the N
+// floats of packed column 0's mirrored-term filter (residue-major as well).
+template <int N>
+__global__ void k_plane_filters(const float* __restrict__ f, float* __restrict__ fr, int L, int K) {
+    constexpr int NA = 16, NB = N / NA;
+    const size_t per = (size_t)(L + 1) * N;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < per * K; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t k = i / per, r = i % per;
+        int ra, j;
+        if (r < (size_t)N * L) {
+            ra = (int)(r / L);
+            j = (int)(r % L);
+        } else {
+            ra = (int)(r - (size_t)N * L);
+            j = L;
+        }
+        const int xi = NB * (ra % NA) + ra / NA;
+        fr[i] = f[k * per + (size_t)j * N + xi];
+    }
+}
+
+// out[b][k] (N x M real) = row c2r of colIFFT(filter_k (.) X[b]) for plane b K + k, from the
+// residue-major spectra Xr and filters fr (real filter sets). Consecutive planes go to one XCD in
+// contiguous runs, so that the planes in flight on an XCD share their image's spectra in its L2.
+template <int N, int M>
+__global__ __launch_bounds__((PlaneCfg<N, M>::THREADS)) void k_plane_fwd(const float2* __restrict__ Xr,
+                                                                        const float* __restrict__ fr,
+                                                                        float* __restrict__ out, int K,
+                                                                        const float2* __restrict__ twN,
+                                                                        const float2* __restrict__ twM) {
+    using C = PlaneCfg<N, M>;
+    constexpr int L = C::L, NA = C::NA, NB = C::NB, CR = C::CR, PITCH = C::PITCH;
+    extern __shared__ float2 lds[];
+    const int tid = (int)threadIdx.x;
+    int plane = (int)blockIdx.x;
+    {
+        const int per = (int)gridDim.x / 8;
+        if (plane < per * 8) plane = (plane % 8) * per + plane / 8;
+    }
+    const int b = plane / K, k = plane % K;
+    const float2* xs = Xr + (size_t)b * L * N;
+    const float* fa = fr + (size_t)k * (L + 1) * N;
+    float2* stw = lds + C::ROWS * PITCH;  // the row FFT's twiddles exp(-2 pi i m / M), m < M
+    float2* sx0 = stw + M;                // packed column 0 of X (N, residue-major)
+    float* sbe = reinterpret_cast<float*>(sx0 + N);  // its mirrored-term filter (N, residue-major)
+    // First step: wavefront bb (xi = NB a + bb), columns lane + 64 h; residues c < CR go to LDS row
+    // c NB + bb, the rest wait in registers. The first half's inputs and the tables are loaded
+    // before the block's first barrier, the other halves' right after it; packed column 0's
+    // mirrored term beta(xi) conj X(-xi) takes X(-xi) from the wavefront that loaded it, through LDS.
+    const int bb = __builtin_amdgcn_readfirstlane(tid / 64), lane = tid % 64;
+    const float2* xb = xs + (size_t)bb * NA * L;
+    const float* fb = fa + (size_t)bb * NA * L;
+    float2 xv[C::HALVES][NA];
+    float fv[C::HALVES][NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        xv[0][a] = xb[(unsigned)(a * L + lane)];
+        fv[0][a] = fb[(unsigned)(a * L + lane)];
+    }
+    float2 tm = make_float2(0.0f, 0.0f);
+    float be = 0.0f;
+    if (tid < M) tm = twM[tid];
+    if (tid < N) be = fa[(size_t)N * L + tid];
+    if (lane == 0) {
+#pragma unroll
+        for (int a = 0; a < NA; ++a) sx0[bb * NA + a] = xv[0][a];
+    }
+    if (tid < M) stw[tid] = tm;
+    if (tid < N) sbe[tid] = be;
+    __syncthreads();
+#pragma unroll
+    for (int h = 1; h < C::HALVES; ++h)
+#pragma unroll
+        for (int a = 0; a < NA; ++a) {
+            const unsigned o = (unsigned)(a * L + lane + 64 * h);
+            xv[h][a] = xb[o];
+            fv[h][a] = fb[o];
+        }
+    float2 keep[C::HALVES][NA - CR];
+#pragma unroll
+    for (int h = 0; h < C::HALVES; ++h) {
+        const int j = lane + 64 * h;
+        float2 y[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) y[a] = cscale(xv[h][a], fv[h][a]);
+        if (j == 0) {
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int xm = (N - (NB * a + bb)) & (N - 1);
+                y[a] = cadd(y[a], cscale(cconj(sx0[(xm % NB) * NA + xm / NB]), sbe[bb * NA + a]));
+            }
+        }
+        dft16<true>(y);
+#pragma unroll
+        for (int c = 1; c < NA; ++c) y[c] = cmul(y[c], cconj(twN[bb * c]));
+#pragma unroll
+        for (int c = 0; c < CR; ++c) lds[(c * NB + bb) * PITCH + j] = y[c];
+#pragma unroll
+        for (int c = CR; c < NA; ++c) keep[h][c - CR] = y[c];
+    }
+    __syncthreads();
+    // The rounds stay a loop: unrolled, the compiler keeps the LDS addresses of both rounds live
+    // at once and spills.
+#pragma unroll 1
+    for (int R = 0; R < C::ROUNDS; ++R) {
+        float2* ld = lds;
+        if (R > 0) {
+#pragma unroll
+            for (int h = 0; h < C::HALVES; ++h)
+#pragma unroll
+                for (int c = 0; c < CR; ++c) ld[(c * NB + bb) * PITCH + lane + 64 * h] = keep[h][c];
+            __syncthreads();
+        }
+        {
+            // last step: thread (column j, residue cl + CR R) over its NB rows, in place
+            const int j = tid % L, cl = tid / L;
+            float2 z[NB];
+#pragma unroll
+            for (int x = 0; x < NB; ++x) z[x] = ld[(cl * NB + x) * PITCH + j];
+            dft16<true>(z);
+#pragma unroll
+            for (int d = 0; d < NB; ++d) ld[(cl * NB + d) * PITCH + j] = z[d];
+        }
+        __syncthreads();
+        {
+            // Row c2r, two rows per FFT: with X1, X2 the Hermitian spectra of LDS rows 2p and 2p + 1
+            // (plane rows cl + CR R + NA d, LDS row cl NB + d), the M-point IDFT of X1 + i X2 has
+            // row 1 as its real part and row 2 as its imaginary part. 16 threads per pair, one
+            // wavefront; the pair's two LDS rows are its FFT scratch.
+            const int p2 = tid / 16, t16 = tid % 16;
+            float2* s = ld + 2 * p2 * PITCH;
+            const float2* s1 = s;
+            const float2* s2 = s + PITCH;
+            const float2* stw_r = ld + (stw - lds);
+            float2 v[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int kk = t16 + 16 * q;
+                if (q < 8) {  // kk < L: X1 + i X2; kk == 0: the real DC bins
+                    float2 a1 = s1[kk], a2 = s2[kk];
+                    if (kk == 0) {
+                        a1 = make_float2(a1.x, 0.0f);
+                        a2 = make_float2(a2.x, 0.0f);
+                    }
+                    v[q] = make_float2(a1.x - a2.y, a1.y + a2.x);
+                } else {  // kk >= L: conj X1(M - kk) + i conj X2(M - kk); kk == L: the real Nyquist bins
+                    const int m = (M - kk) & (L - 1);
+                    float2 a1 = s1[m], a2 = s2[m];
+                    if (m == 0) {
+                        a1 = make_float2(a1.y, 0.0f);
+                        a2 = make_float2(a2.y, 0.0f);
+                    }
+                    v[q] = make_float2(a1.x + a2.y, a2.x - a1.y);
+                }
+            }
+            wave_sync();
+            fft<M, 16, true>(v, s, t16, stw_r);
+            const int ra = 2 * p2, rb = 2 * p2 + 1;
+            float* d1 = out + ((size_t)plane * N + (ra / NB) + CR * R + NA * (ra % NB)) * M;
+            float* d2 = out + ((size_t)plane * N + (rb / NB) + CR * R + NA * (rb % NB)) * M;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                __builtin_nontemporal_store(v[q].x, d1 + t16 + 16 * q);
+                __builtin_nontemporal_store(v[q].y, d2 + t16 + 16 * q);
+            }
+        }
+        if (R + 1 < C::ROUNDS) __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------- dispatch
 
 template <typename F>
@@ -774,6 +1002,29 @@ hipError_t cols_inv_pc(const DevPlan& d, const float2* U, float2* V, int nimg, c
     return cols_inv_t<N, PW, ColPts<N>::value>(d, U, V, nimg, filt, part, st);
 }
 
+// whole-plane forward: column spectra of the images (residue-major), then one workgroup per plane
+template <int N>
+hipError_t cols_spec_t(const DevPlan& d, const float2* A, float2* Xr, int nimg, float scale, hipStream_t st) {
+    constexpr int PW = 16, PP = ColPts<N>::value;
+    using S = ColCfg<N, PW, PP>;
+    const int npan = d.L / PW;
+    hipError_t e = set_lds(k_cols_spec<N, PW, PP>, S::LDS);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cols_spec<N, PW, PP>), dim3((unsigned)((size_t)npan * nimg)), dim3(S::THREADS), S::LDS, st, A,
+                       Xr, d.L, npan, d.twN, scale);
+    return hipGetLastError();
+}
+
+template <int N, int M>
+hipError_t plane_fwd_t(const DevPlan& d, const float2* Xr, float* out, int nimg, const float* fr, hipStream_t st) {
+    using C = PlaneCfg<N, M>;
+    hipError_t e = set_lds(k_plane_fwd<N, M>, C::LDS);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_plane_fwd<N, M>), dim3((unsigned)((size_t)nimg * d.K)), dim3(C::THREADS), C::LDS, st, Xr, fr,
+                       out, d.K, d.twN, d.twM);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int col_points_alternative(int N) {
@@ -910,6 +1161,25 @@ hipError_t launch_cols_fwd(const DevPlan& d, const float2* A, float2* T, int nim
 hipError_t launch_cols_inv(const DevPlan& d, const float2* U, float2* V, int nimg, const void* filt, float2* part,
                            hipStream_t st) {
     SHEAR_COLS_SWITCH(d.pw_inv, 8, cols_inv_pc, d, U, V, nimg, filt, part, st)
+}
+
+bool plane_fwd_supported(const DevPlan& d) { return d.real && d.N == 256 && d.M == 256; }
+
+hipError_t launch_plane_filters(const DevPlan& d, const float* filt, float* fr, hipStream_t st) {
+    if (!plane_fwd_supported(d)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_plane_filters<256>, dim3(1024), dim3(256), 0, st, filt, fr, d.L, d.K);
+    return hipGetLastError();
+}
+
+hipError_t launch_cols_spec(const DevPlan& d, const float2* A, float2* Xr, int nimg, float scale, hipStream_t st) {
+    if (!plane_fwd_supported(d)) return hipErrorInvalidValue;
+    return cols_spec_t<256>(d, A, Xr, nimg, scale, st);
+}
+
+hipError_t launch_plane_fwd(const DevPlan& d, const float2* Xr, float* out, int nimg, const float* fr,
+                            hipStream_t st) {
+    if (!plane_fwd_supported(d)) return hipErrorInvalidValue;
+    return plane_fwd_t<256, 256>(d, Xr, out, nimg, fr, st);
 }
 
 hipError_t launch_zero_u32(unsigned* p, int n, hipStream_t st) {

@@ -33,6 +33,7 @@ struct shear_system {
     const void* filt_fwd = nullptr;
     const void* filt_inv = nullptr;
     const void* filt_adj = nullptr;
+    const float* filt_plane = nullptr;  // forward set, residue-major (whole-plane forward), or null
     const float* rms_dev = nullptr;  // RMS_k as float (learned shrinkage)
     shear::DevPlan plan;
     void* ws = nullptr;
@@ -186,7 +187,10 @@ int finish_system(shear_system* s, std::string& why) {
     const size_t b_f = al(ffwd.size() * sizeof(float));
     std::vector<float> rms32(s->rms.begin(), s->rms.end());
     const size_t b_r = al((size_t)K * sizeof(float));
-    const size_t total = b_tw + 3 * b_f + b_r;
+    // the forward filter set once more, residue-major, where the whole-plane forward is compiled
+    // (the test of shear::plane_fwd_supported)
+    const bool plane = s->real && N == 256 && M == 256;
+    const size_t total = b_tw + 3 * b_f + b_r + (plane ? b_f : 0);
     hipError_t e = hipMalloc(&s->dev_block, total);
     if (e != hipSuccess) {
         s->dev_block = nullptr;
@@ -217,6 +221,15 @@ int finish_system(shear_system* s, std::string& why) {
     s->filt_inv = base + b_tw + b_f;
     s->filt_adj = base + b_tw + 2 * b_f;
     s->rms_dev = (const float*)(base + b_tw + 3 * b_f);
+    if (plane) {
+        float* fr = (float*)(base + b_tw + 3 * b_f + b_r);
+        if ((e = shear::launch_plane_filters(s->plan, (const float*)s->filt_fwd, fr, nullptr)) != hipSuccess ||
+            (e = hipStreamSynchronize(nullptr)) != hipSuccess) {
+            why = std::string("reordering the forward filters failed: ") + hipGetErrorString(e);
+            return SHEAR_E_HIP;
+        }
+        s->filt_plane = fr;
+    }
     if ((e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->device)) != hipSuccess) {
         why = std::string("querying the compute-unit count failed: ") + hipGetErrorString(e);
         return SHEAR_E_HIP;
@@ -575,8 +588,20 @@ int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, voi
                          [&] { return shear::launch_rows_r2c(d, x, A, batch, false, st); });
     if (e != hipSuccess) return hip_fail(e, "row r2c launch");
     const float scale = (float)(1.0 / (double)img);  // 1/(N M): a power of two, exact
+    const bool plane = d.plane_fwd && shear::plane_fwd_supported(d);
     for (int b0 = 0; b0 < batch; b0 += chunk) {
         const int nb = std::min(chunk, batch - b0);
+        if (plane) {
+            // the chunk's column spectra (nb planes) take the room of its K nb exchange planes
+            e = timed(s, SHEAR_KERNEL_COLS_FWD, st,
+                      [&] { return shear::launch_cols_spec(d, A + (size_t)b0 * pb, T, nb, scale, st); });
+            if (e != hipSuccess) return hip_fail(e, "column spectra launch");
+            e = timed(s, SHEAR_KERNEL_PLANE_FWD, st, [&] {
+                return shear::launch_plane_fwd(d, T, coeffs + (size_t)b0 * d.K * img, nb, s->filt_plane, st);
+            });
+            if (e != hipSuccess) return hip_fail(e, "whole-plane forward launch");
+            continue;
+        }
         e = timed(s, SHEAR_KERNEL_COLS_FWD, st,
                   [&] { return shear::launch_cols_fwd(d, A + (size_t)b0 * pb, T, nb, s->filt_fwd, scale, st); });
         if (e != hipSuccess) return hip_fail(e, "column pass launch");
@@ -927,7 +952,10 @@ int shear_inpaint_groups(shear_system* const* systems, int n_groups, const float
 int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int kg_inv, int pc_fwd, int pc_inv) {
     if (!s) return fail(SHEAR_E_INVALID, "system is NULL");
     const int L = s->cols / 2;
+    // pw_fwd == L: the whole plane per workgroup, where that forward is compiled
+    const bool plane = shear::plane_fwd_supported(s->plan) && pw_fwd == L;
     for (int pw : {pw_fwd, pw_inv}) {
+        if (pw == pw_fwd && plane) continue;
         if (pw != 0 && pw != 8 && pw != 16) return fail(SHEAR_E_INVALID, "panel width must be 0, 8 or 16");
         if (pw == 16 && L < 16) return fail(SHEAR_E_INVALID, "panel width 16 needs cols >= 32");
     }
@@ -938,7 +966,12 @@ int shear_set_schedule(shear_system* s, int pw_fwd, int pw_inv, int kg_fwd, int 
         if (pc != 0 && pc != pdef && pc != palt)
             return fail(SHEAR_E_INVALID, "points per thread of the " + std::to_string(s->rows) + "-point column FFTs must be 0, " +
                                              std::to_string(pdef) + (palt ? " or " + std::to_string(palt) : std::string()));
-    if (pw_fwd) s->plan.pw_fwd = pw_fwd;
+    if (plane)
+        s->plan.plane_fwd = true;
+    else if (pw_fwd) {
+        s->plan.pw_fwd = pw_fwd;
+        s->plan.plane_fwd = false;
+    }
     if (pw_inv) s->plan.pw_inv = pw_inv;
     if (kg_fwd) s->plan.kg_fwd = kg_fwd;
     if (kg_inv) s->plan.kg_inv = kg_inv;
@@ -1010,11 +1043,15 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
     for (int dir = 0; dir < 2 && e == hipSuccess && call_rc == SHEAR_OK; ++dir) {
         struct Cand {
             int pw, kg, pc;
+            bool plane;
         };
         std::vector<Cand> cand;
         for (int pw : pws)
             for (int kg : (dir == 0 ? kgs_fwd : kgs))
-                for (int pc : pcs) cand.push_back({pw, kg, pc});
+                for (int pc : pcs) cand.push_back({pw, kg, pc, false});
+        // the whole-plane forward, where it is compiled (last in the list)
+        if (dir == 0 && shear::plane_fwd_supported(s->plan))
+            cand.push_back({s->plan.pw_fwd, s->plan.kg_fwd, s->plan.pc_fwd, true});
         std::vector<std::vector<float>> times(cand.size());
         for (int round = 0; round <= kRounds && e == hipSuccess && call_rc == SHEAR_OK; ++round) {  // round 0 warms up
             for (size_t ci = 0; ci < cand.size() && e == hipSuccess && call_rc == SHEAR_OK; ++ci) {
@@ -1022,6 +1059,7 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
                 (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = cand[ci].pw;
                 (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = cand[ci].kg;
                 (dir == 0 ? s->plan.pc_fwd : s->plan.pc_inv) = cand[ci].pc;
+                if (dir == 0) s->plan.plane_fwd = cand[ci].plane;
                 if ((e = hipEventRecord(e0, nullptr)) == hipSuccess &&
                     (call_rc = shear_forward(s, xt, ct, batch, nullptr)) == SHEAR_OK &&
                     (call_rc = shear_inverse(s, ct, yt, batch, nullptr)) == SHEAR_OK &&
@@ -1035,6 +1073,11 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
             }
         }
         if (e != hipSuccess || call_rc != SHEAR_OK) break;
+        // The panel schedule is picked among the panel candidates (the denoising and inpainting
+        // column passes use it whichever forward is chosen); the whole-plane forward replaces it
+        // in shear_forward where its median step is faster.
+        size_t n_panel = cand.size();
+        while (n_panel > 0 && cand[n_panel - 1].plane) --n_panel;
         std::vector<float> med(cand.size(), -1.0f);
         float best = -1.0f;
         for (size_t ci = 0; ci < cand.size(); ++ci) {
@@ -1042,13 +1085,13 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
             if (t.empty()) continue;
             std::nth_element(t.begin(), t.begin() + t.size() / 2, t.end());
             med[ci] = t[t.size() / 2];
-            if (best < 0.0f || med[ci] < best) best = med[ci];
+            if (ci < n_panel && (best < 0.0f || med[ci] < best)) best = med[ci];
         }
         // a filter split adds work (the forward repeats a panel's column FFT per group, the inverse
         // writes and adds partial sums), so it is taken only where it is measurably faster: among
         // the candidates within 1 % of the fastest step, the fewest groups, then the fastest
         size_t pick_i = 0;
-        for (size_t ci = 0; ci < cand.size(); ++ci) {
+        for (size_t ci = 0; ci < n_panel; ++ci) {
             if (med[ci] < 0.0f || med[ci] > 1.01f * best) continue;
             if (med[pick_i] < 0.0f || med[pick_i] > 1.01f * best || cand[ci].kg < cand[pick_i].kg ||
                 (cand[ci].kg == cand[pick_i].kg && med[ci] < med[pick_i]))
@@ -1057,6 +1100,8 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
         (dir == 0 ? s->plan.pw_fwd : s->plan.pw_inv) = cand[pick_i].pw;
         (dir == 0 ? s->plan.kg_fwd : s->plan.kg_inv) = cand[pick_i].kg;
         (dir == 0 ? s->plan.pc_fwd : s->plan.pc_inv) = cand[pick_i].pc;
+        if (dir == 0)
+            s->plan.plane_fwd = n_panel < cand.size() && med[n_panel] >= 0.0f && med[n_panel] < med[pick_i];
     }
     s->prof_on = prof;
     if (e0) (void)hipEventDestroy(e0);
@@ -1067,7 +1112,7 @@ int shear_autotune(shear_system* s, int batch, int* pw_fwd, int* pw_inv, int* kg
     if (call_rc != SHEAR_OK) return call_rc;
     if (e != hipSuccess) return hip_fail(e, "autotune launch");
     if (es != hipSuccess) return hip_fail(es, "hipDeviceSynchronize after autotune");
-    if (pw_fwd) *pw_fwd = s->plan.pw_fwd;
+    if (pw_fwd) *pw_fwd = s->plan.plane_fwd ? s->cols / 2 : s->plan.pw_fwd;
     if (pw_inv) *pw_inv = s->plan.pw_inv;
     if (kg_fwd) *kg_fwd = s->plan.kg_fwd;
     if (kg_inv) *kg_inv = s->plan.kg_inv;
