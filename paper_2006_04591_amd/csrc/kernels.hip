@@ -689,9 +689,8 @@ __global__ void k_plane_filters(const float* __restrict__ f, float* __restrict__
     }
 }
 
-// out[b][k] (N x M real) = row c2r of colIFFT(filter_k (.) X[b]) for plane b K + k, from the
-// residue-major spectra Xr and filters fr (real filter sets). Consecutive planes go to one XCD in
-// contiguous runs, so that the planes in flight on an XCD share their image's spectra in its L2.
+// out[b][k] (N x M real) = row c2r of colIFFT(filter_k (.) X[b]) for the gridDim.x = nimg K planes
+// b K + k, from the residue-major spectra Xr and filters fr (real filter sets).
 template <int N, int M>
 __global__ __launch_bounds__((PlaneCfg<N, M>::THREADS)) void k_plane_fwd(const float2* __restrict__ Xr,
                                                                         const float* __restrict__ fr,
@@ -702,10 +701,19 @@ __global__ __launch_bounds__((PlaneCfg<N, M>::THREADS)) void k_plane_fwd(const f
     constexpr int L = C::L, NA = C::NA, NB = C::NB, CR = C::CR, PITCH = C::PITCH;
     extern __shared__ float2 lds[];
     const int tid = (int)threadIdx.x;
-    int plane = (int)blockIdx.x;
+    // Plane order: each XCD takes a contiguous run of the sequence, and the sequence walks the
+    // images in groups of G, filter-major within a group, so that the blocks in flight on an XCD
+    // share a few images' spectra and a few filters in its L2 (rather than one image and as many
+    // filters as blocks).
+    int plane;
     {
+        constexpr int G = 4;
+        int i = (int)blockIdx.x;
         const int per = (int)gridDim.x / 8;
-        if (plane < per * 8) plane = (plane % 8) * per + plane / 8;
+        if (i < per * 8) i = (i % 8) * per + i / 8;
+        const int nimg = (int)gridDim.x / K, g0 = i / (G * K) * G, gn = min(G, nimg - g0);
+        const int r = i - g0 * K;
+        plane = (g0 + r % gn) * K + r / gn;
     }
     const int b = plane / K, k = plane % K;
     const float2* xs = Xr + (size_t)b * L * N;
