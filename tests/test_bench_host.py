@@ -33,6 +33,14 @@ def test_algorithmic_bytes_of_the_headline_step():
                                "rows_c2r_images"))
     assert per_kernel == want
     assert bench.kernel_algorithmic_bytes("rows_c2r_coeffs", K, True) == B * K * N * M * 4
+    # the whole-plane forward: its plane kernel reads the filters and writes the coefficients, the
+    # column-spectra pass moves none of the method's bytes; the step's total is the same
+    plane = sum(bench.kernel_algorithmic_bytes(k, K, True, plane_fwd=True)
+                for k in ("rows_r2c_images", "cols_fwd", "plane_fwd", "rows_r2c_coeffs", "cols_inv",
+                          "rows_c2r_images"))
+    assert plane == want
+    assert bench.kernel_algorithmic_bytes("cols_fwd", K, True, plane_fwd=True) == 0
+    assert bench.exchange_bytes("plane_fwd", K, plane_fwd=True) == B * N * (M // 2) * 8
 
 
 def _counter_csv(path, rows):
