@@ -130,7 +130,9 @@ int shear_forward(shear_system* s, const float* x, float* coeffs, int batch, voi
 
 /* shear_forward for callers that cannot allocate device memory (code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * same transform, bitwise equal to shear_forward, computed through a fixed
+ * same transform, bitwise equal to shear_forward under a panel schedule (it
+ * always takes the panel form; the whole-plane forward that shear_set_schedule
+ * can select for shear_forward agrees with it to rounding), computed through a fixed
  * 64 MiB device scratch array that the library holds on each GPU it runs on
  * until the process ends, instead of the system's workspace. It calls no
  * hipMalloc, hipFree or other allocating routine and never synchronises.
