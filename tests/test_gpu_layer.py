@@ -54,17 +54,20 @@ def test_layer_gradient_32x32(gpu):
         assert abs(lhs - rhs) <= 1e-5 * abs(rhs)
 
 
-def test_layer_config4(gpu):
-    """32 images of 256x256 (one channel), 33 filters, upstream gradient N(0, 1)."""
+@pytest.mark.parametrize("forward", ["panel", "whole-plane"])
+def test_layer_config4(gpu, forward):
+    """32 images of 256x256 (one channel), 33 filters, upstream gradient N(0, 1); the forward in its
+    panel form and in the whole-plane form the autotuner may pick at this size."""
     from paper_2006_04591_amd import ShearletLayer
 
-    _say("case: layer 256x256 J=3 K=33 B=32")
+    _say(f"case: layer 256x256 J=3 K=33 B=32, {forward} forward")
     ref = OF.build_system(256, 256, 3)
     x = synth.cartoon_batch(32, 256, 256, config=4, sigma=0.0)[:, None]
     rng = np.random.default_rng(4)
     g = rng.standard_normal((32, 33, 256, 256)).astype(np.float32)
     layer = ShearletLayer(256, 256, 3)
     assert layer.K == 33
+    layer.system.set_schedule(128 if forward == "whole-plane" else 16)
     xt = _to(x, gpu).requires_grad_(True)
     c = layer(xt)
     (c * _to(g, gpu)).sum().backward()
