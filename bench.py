@@ -111,15 +111,18 @@ COUNTER_WORKLOAD = "16x512x512x49"  # batch x rows x cols x filters the stored c
 def counters_from_profiles(kind: str, path: str = "", src=None, workload: str = COUNTER_WORKLOAD):
     """Counter figures per launch of a kernel kind measured with rocprofv3 (profiles/counters.json:
     calibrated HBM bytes, VALU instructions), if they were taken on this workload (batch x rows x
-    cols x filters) and the kernel sources have not changed since; else None."""
+    cols x filters: the record's own, or one under "other_workloads") and the kernel sources have
+    not changed since; else None."""
     path = path or os.path.join(ROOT, "profiles", "counters.json")
     try:
         with open(path) as fh:
             rec = json.load(fh)
-        if rec.get("kernel_sources_sha256") != source_digest(src) or rec.get("workload") != workload:
+        if rec.get("kernel_sources_sha256") != source_digest(src):
             return None
-        return rec["kernels"].get(kind)
-    except (OSError, ValueError, KeyError):
+        if rec.get("workload") == workload:
+            return rec["kernels"].get(kind)
+        return rec.get("other_workloads", {}).get(workload, {}).get("kernels", {}).get(kind)
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
 
 
@@ -504,11 +507,14 @@ def copy_calibration(mib: int) -> int:
 
 
 def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_write_csv: str, cal_bytes: int,
-                    out_path: str = "", src=None, valu_csv: str = "") -> int:
+                    out_path: str = "", src=None, valu_csv: str = "", workload: str = COUNTER_WORKLOAD) -> int:
     """Writes profiles/counters.json: per-kernel HBM bytes per launch from rocprofv3 counter CSVs
     (FETCH_SIZE and WRITE_SIZE in KiB per dispatch), each scaled by the factor that makes the
     same counter read cal_bytes for the calibration copy kernel, and (valu_csv) the VALU, LDS and
-    vector-memory instruction counts per launch (SQ_INSTS_*, summed over the counter's instances)."""
+    vector-memory instruction counts per launch (SQ_INSTS_*, summed over the counter's instances).
+    The headline workload's figures form the record; another workload's ("BxNxMxK", its kernels
+    identified by their row length M) go under "other_workloads" of an existing record taken on the
+    same kernel sources, which they require."""
     import csv
     import statistics
 
@@ -535,8 +541,10 @@ def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_writ
     write = per_kernel(write_csv, "WRITE_SIZE")
     insts = {c: per_kernel(valu_csv, c) for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD",
                                                  "SQ_INSTS_VMEM_WR")} if valu_csv else {}
-    kinds = {"k_rows_r2c<512, 0": "rows_r2c_images", "k_cols_fwd<": "cols_fwd", "k_rows_c2r<512, 1": "rows_c2r_coeffs",
-             "k_rows_r2c<512, 1": "rows_r2c_coeffs", "k_cols_inv<": "cols_inv", "k_rows_c2r<512, 0": "rows_c2r_images"}
+    mcols = int(workload.split("x")[2])
+    kinds = {f"k_rows_r2c<{mcols}, 0": "rows_r2c_images", "k_cols_fwd<": "cols_fwd", "k_cols_spec<": "cols_fwd",
+             f"k_rows_c2r<{mcols}, 1": "rows_c2r_coeffs", f"k_rows_r2c<{mcols}, 1": "rows_r2c_coeffs",
+             "k_cols_inv<": "cols_inv", f"k_rows_c2r<{mcols}, 0": "rows_c2r_images", "k_plane_fwd<": "plane_fwd"}
     out = {}
     for name in fetch:
         kind = next((v for k, v in kinds.items() if k in name), None)
@@ -550,9 +558,22 @@ def traffic_summary(fetch_csv: str, write_csv: str, cal_fetch_csv: str, cal_writ
             key = {"SQ_INSTS_VALU": "valu_wave_instructions"}.get(c, c.lower().replace("sq_insts_", "") +
                                                                    "_wave_instructions")
             out[kind][key] = vals.get(name)
-    rec = {"kernel_sources_sha256": source_digest(src), "workload": COUNTER_WORKLOAD, "fetch_scale": ff, "write_scale": fw,
-           "calibration_bytes": cal_bytes, "kernels": out}
     path = out_path or os.path.join(ROOT, "profiles", "counters.json")
+    digest = source_digest(src)
+    if workload == COUNTER_WORKLOAD:
+        rec = {"kernel_sources_sha256": digest, "workload": COUNTER_WORKLOAD, "fetch_scale": ff, "write_scale": fw,
+               "calibration_bytes": cal_bytes, "kernels": out}
+    else:
+        try:
+            with open(path) as fh:
+                rec = json.load(fh)
+        except (OSError, ValueError):
+            rec = None
+        if not rec or rec.get("kernel_sources_sha256") != digest:
+            print(f"bench.py: no counter record of the current kernel sources in {path} to add {workload} to",
+                  file=sys.stderr)
+            return 1
+        rec.setdefault("other_workloads", {})[workload] = {"fetch_scale": ff, "write_scale": fw, "kernels": out}
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec, indent=1))
@@ -563,9 +584,10 @@ def main() -> int:
     if len(sys.argv) > 1 and sys.argv[1] == "--copy-calibration":
         return copy_calibration(int(sys.argv[2]))
     if len(sys.argv) > 1 and sys.argv[1] == "--counter-summary":
-        # fetch.csv write.csv cal_fetch.csv cal_write.csv cal_bytes [valu.csv]
+        # fetch.csv write.csv cal_fetch.csv cal_write.csv cal_bytes [valu.csv [BxNxMxK]]
         a = sys.argv[2:]
-        return traffic_summary(a[0], a[1], a[2], a[3], int(a[4]), valu_csv=a[5] if len(a) > 5 else "")
+        return traffic_summary(a[0], a[1], a[2], a[3], int(a[4]), valu_csv=a[5] if len(a) > 5 else "",
+                               workload=a[6] if len(a) > 6 else COUNTER_WORKLOAD)
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)

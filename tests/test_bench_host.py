@@ -94,6 +94,23 @@ def test_counter_summary_calibrates_and_keys_by_source(tmp_path):
     assert bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src),
                                        workload="32x256x256x33") is None
     assert bench.valu_bound("rows_c2r_coeffs", 0.2766, path=str(out), src=str(src), workload="32x256x256x33") is None
+    # ... until that workload's own counters are added beside the record (its 256-column kernels)
+    k256 = "void shear::(anonymous namespace)::k_plane_fwd<256, 256>(HIP_vector_type<float, 2u> const*, float*)"
+    _counter_csv(tmp_path / "fetch2.csv", [
+        {"Dispatch_Id": 3, "Kernel_Name": k256, "Counter_Name": "FETCH_SIZE", "Counter_Value": 100.0},
+        {"Dispatch_Id": 3, "Kernel_Name": kern, "Counter_Name": "FETCH_SIZE", "Counter_Value": 7.0}])
+    _counter_csv(tmp_path / "write2.csv", [
+        {"Dispatch_Id": 3, "Kernel_Name": k256, "Counter_Name": "WRITE_SIZE", "Counter_Value": 300.0}])
+    assert bench.traffic_summary(str(tmp_path / "fetch2.csv"), str(tmp_path / "write2.csv"), str(tmp_path / "calf.csv"),
+                                 str(tmp_path / "calw.csv"), cal, out_path=str(out), src=str(src),
+                                 workload="32x256x256x33") == 0
+    got = bench.traffic_from_profiles("plane_fwd", 1.0, path=str(out), src=str(src), workload="32x256x256x33")
+    assert got == pytest.approx(2.0 * 1024 * 100.0 + 1024 * 300.0)
+    # the 512-column kernel is not one of this workload's kinds, and the headline record is unchanged
+    assert bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src),
+                                       workload="32x256x256x33") is None
+    assert bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src)) == pytest.approx(
+        ent["fetch_bytes"] + ent["write_bytes"])
     # a changed kernel source makes the stored counters stale
     src.write_text("// another version of the kernels\n")
     assert bench.traffic_from_profiles("rows_c2r_coeffs", 1.0, path=str(out), src=str(src)) is None
